@@ -1,0 +1,334 @@
+"""ADER-DG element update with gravity free surface and clustered LTS (oracle).
+
+Test infrastructure only; see ``oracle/__init__``. Plain FP64, vectorised
+over elements with numpy; every integral is evaluated at physical quadrature
+points (no precomputed reference stiffness or flux matrices, no rotation T).
+
+Method (Sec. 4 of the paper):
+  * semi-discrete DG form on each element with an orthonormal modal basis
+    (Sec. 4.1, semi-discrete form); the mass matrix is the identity in the
+    reference measure;
+  * ADER predictor: Taylor expansion in time whose derivatives come from the
+    Cauchy-Kowalevski procedure, each time derivative being the L2 projection
+    of -(A q_x + B q_y + C q_z) (Sec. 4.1, Taylor expansion);
+  * ADER corrector: the Taylor series integrated over the step and inserted
+    into the time-integrated weak form (Sec. 4.1);
+  * Godunov flux from the exact Riemann solution (Sec. 4.2), boundary
+    conditions through ghost states (Sec. 4.3);
+  * gravity free surface: per-point ODE for eta and its time integral H, and
+    the time-integrated boundary state (Sec. 4.3, coupled ODE system);
+  * rate-2 clustered local time stepping (Sec. 4.4).
+
+Readings where the paper is silent (the design notes list them all):
+  * cluster c holds dt_K in [2^c dt_min, 2^(c+1) dt_min), capped at
+    max_clusters-1, then lowered until face neighbours differ by at most 1;
+  * the gravity ODE is integrated exactly (Taylor series of the linear ODE)
+    instead of with a 7th-order Runge-Kutta method;
+  * p- on a gravity face is -n.s.n.
+"""
+from __future__ import annotations
+
+import functools
+import math
+
+import numpy as np
+
+from . import basis as bas
+from . import quadrature as quad
+from .mesh import Geometry, adjacency, ref_face_points, FACE_VERTS
+from .physics import jacobians, stress_tensor
+from .riemann import godunov_flux, ghost_state, gravity_eta_step, flux_of_state
+
+FACE_INTERIOR, FACE_PERIODIC, FACE_GRAVITY, FACE_ABSORBING, FACE_WALL, FACE_FREE = range(6)
+
+# tensor contractions written as einsum; 'optimize' lets numpy pair them through BLAS
+ein = functools.partial(np.einsum, optimize=True)
+
+
+def taylor_weights(N: int, a: float, b: float) -> np.ndarray:
+    """w_k = (b^(k+1) - a^(k+1)) / (k+1)!: integral over [a, b] of t^k / k!."""
+    return np.array([(b ** (k + 1) - a ** (k + 1)) / math.factorial(k + 1) for k in range(N + 1)])
+
+
+def assign_clusters(dt_elem, nb, max_clusters):
+    """Rate-2 clustering (Sec. 4.4) with the neighbour-difference rule."""
+    dt_min = float(dt_elem.min())
+    c = np.floor(np.log2(dt_elem / dt_min)).astype(np.int64)
+    c = np.clip(c, 0, max_clusters - 1)
+    E = c.size
+    changed = True
+    while changed:
+        changed = False
+        for e in range(E):
+            for i in range(4):
+                j = nb[e, i]
+                if j >= 0 and c[e] > c[j] + 1:
+                    c[e] = c[j] + 1
+                    changed = True
+    return c, dt_min
+
+
+class Oracle:
+    """Plain FP64 ADER-DG solver on one mesh.
+
+    Arguments mirror the library's set-up call: vertex coordinates [V, 3],
+    tetrahedra [E, 4], face kinds [E, 4], period [3], per-element rho, lambda,
+    mu, the polynomial degree N (convergence order N+1), the CFL constant C
+    in dt = C/(2N+1) h / c_p, gravity g and the number of LTS clusters.
+    """
+
+    def __init__(self, xyz, tet, face_kind, period, rho, lam, mu, N, *, cfl=0.35,
+                 g=9.81, max_clusters=1, cluster_of=None):
+        self.N = N
+        self.B = bas.n_basis(N)
+        self.geo = Geometry(xyz, tet)
+        self.face_kind = np.asarray(face_kind, dtype=np.int64)
+        self.nb, self.nbf, self.shift = adjacency(tet, face_kind, self.geo.xyz, period)
+        self.rho = np.asarray(rho, dtype=np.float64)
+        self.lam = np.asarray(lam, dtype=np.float64)
+        self.mu = np.asarray(mu, dtype=np.float64)
+        self.g = float(g)
+        E = self.geo.tet.shape[0]
+        self.E = E
+        self.A = np.stack([jacobians(self.lam[e], self.mu[e], self.rho[e]) for e in range(E)])
+        self.cp = np.sqrt((self.lam + 2 * self.mu) / self.rho)
+        self.Zp = self.rho * self.cp
+
+        # quadrature rules and basis tables
+        self.vpts, self.vw = quad.tet_rule(N + 2)
+        self.phi_v = bas.eval_basis(N, self.vpts)           # [q, B]
+        self.dphi_v = bas.eval_grad(N, self.vpts)           # [q, B, 3]
+        self.fst, self.fw = quad.tri_rule(N + 2)
+        self.phi_f = [bas.eval_basis(N, ref_face_points(i, self.fst)) for i in range(4)]
+        self.gst, self.gw = quad.tri_rule(N + 1)
+        self.phi_g = [bas.eval_basis(N, ref_face_points(i, self.gst)) for i in range(4)]
+
+        # time steps and clusters (Sec. 4.4)
+        self.dt_elem = cfl / (2 * N + 1) * self.geo.h / self.cp
+        if cluster_of is None:
+            self.cluster, self.dt_min = assign_clusters(self.dt_elem, self.nb, max_clusters)
+        else:
+            self.cluster = np.asarray(cluster_of, dtype=np.int64)
+            self.dt_min = float(self.dt_elem.min())
+        self.n_clusters = int(self.cluster.max()) + 1
+        self.members = [np.nonzero(self.cluster == c)[0] for c in range(self.n_clusters)]
+        self.pos = np.empty(E, dtype=np.int64)
+        for c in range(self.n_clusters):
+            self.pos[self.members[c]] = np.arange(self.members[c].size)
+
+        # gravity faces, sorted by (element, local face)
+        ge, gf = np.nonzero(self.face_kind == FACE_GRAVITY)
+        self.grav_elem, self.grav_face = ge, gf
+        if ge.size and np.any(self.mu[ge] != 0.0):
+            raise ValueError("gravity face on an elastic element")
+        self.eta = np.zeros((ge.size, self.gst.shape[0]))
+
+        self.Q = np.zeros((E, self.B, 9))
+        self._nb_cache = {}
+        self.time = 0.0
+        self.updates = 0
+
+    # ------------------------------------------------------------------
+    def predict(self, elems):
+        """Cauchy-Kowalevski time derivatives D^0..D^N of elements -> [n, N+1, B, 9]."""
+        D = [self.Q[elems]]
+        n = elems.size
+        nq = self.vw.size
+        JinvT = np.swapaxes(self.geo.Jinv[elems], 1, 2)[:, None]          # [n, 1, e, d]
+        A_rt = np.transpose(self.A[elems], (0, 1, 3, 2)).reshape(n, 27, 9)  # [n, (e p), r]
+        dphi = np.transpose(self.dphi_v, (0, 2, 1)).reshape(nq * 3, self.B)  # [(q d), b]
+        proj = (self.phi_v * self.vw[:, None]).T                             # [b, q]
+        for _ in range(self.N):
+            # reference gradient of q_k at the volume points, then the chain rule
+            gref = np.matmul(dphi, D[-1]).reshape(n, nq, 3, 9)               # [n, q, d, p]
+            gphys = np.matmul(JinvT, gref)                                   # [n, q, e, p]
+            # f = -(A q_x + B q_y + C q_z) at the points, then its L2 projection
+            f = -np.matmul(gphys.reshape(n, nq, 27), A_rt)                   # [n, q, r]
+            D.append(np.matmul(proj, f))
+        return np.stack(D, axis=1)
+
+    def eval_at(self, elems, x, coeff):
+        """Evaluate polynomials coeff[n, B, 9] of elements at physical points x[n, q, 3]."""
+        xi = self.geo.to_ref(elems[:, None], x)
+        n, q = x.shape[:2]
+        phi = bas.eval_basis(self.N, xi.reshape(-1, 3)).reshape(n, q, self.B)
+        return ein("nqb,nbp->nqp", phi, coeff)
+
+    def _neighbour_basis(self, c, i):
+        """Neighbour basis values at the flux points of face i of cluster c's elements.
+
+        The physical flux points (shifted across periodic faces) are mapped
+        into each neighbour's reference element; cached since the mesh is fixed.
+        """
+        key = (c, i)
+        if key not in self._nb_cache:
+            elems = self.members[c]
+            kind = self.face_kind[elems, i]
+            inter = np.nonzero((kind == FACE_INTERIOR) | (kind == FACE_PERIODIC))[0]
+            x = self.geo.face_points(elems[inter], np.full(inter.size, i), self.fst)
+            xs = x + self.shift[elems[inter], i][:, None, :]
+            J = self.nb[elems[inter], i]
+            xi = self.geo.to_ref(J[:, None], xs)
+            n, q = xs.shape[:2]
+            self._nb_cache[key] = bas.eval_basis(self.N, xi.reshape(-1, 3)).reshape(n, q, self.B)
+        return self._nb_cache[key]
+
+    # ------------------------------------------------------------------
+    def _integral(self, hist, elems, a, b):
+        """Time integral over [a, b] (integer sub-step units) of elements' expansions."""
+        out = np.zeros((elems.size, self.B, 9))
+        cl = self.cluster[elems]
+        for c in np.unique(cl):
+            sel = np.nonzero(cl == c)[0]
+            rows = self.pos[elems[sel]]
+            for (t0, length, D) in hist[c]:
+                lo, hi = max(a, t0), min(b, t0 + length)
+                if hi <= lo:
+                    continue
+                w = taylor_weights(self.N, (lo - t0) * self.dt_min, (hi - t0) * self.dt_min)
+                out[sel] += np.tensordot(w, D[rows], axes=(0, 1))
+        return out
+
+    def correct(self, c, hist, t0):
+        """Corrector of cluster c over [t0, t0 + 2^c] (sub-step units)."""
+        elems = self.members[c]
+        length = 1 << c
+        dt = length * self.dt_min
+        own = hist[c][-1][2][np.arange(elems.size)]
+        I = np.tensordot(taylor_weights(self.N, 0.0, dt), own, axes=(0, 1))
+        n = elems.size
+        nq = self.vw.size
+        # volume term: sum_q w_q grad_x(phi_l) . (A_e I)(x_q)
+        Iq = np.matmul(self.phi_v, I)                                        # [n, q, p]
+        A_p = np.transpose(self.A[elems], (0, 3, 1, 2)).reshape(n, 9, 27)   # [n, p, (e r)]
+        AI = np.matmul(Iq, A_p).reshape(n, nq, 3, 9)                         # [n, q, e, r]
+        G = np.matmul(self.geo.Jinv[elems][:, None], AI)                     # [n, q, d, r]
+        Wd = (np.transpose(self.dphi_v, (0, 2, 1)) * self.vw[:, None, None]).reshape(nq * 3, self.B).T
+        dQ = np.matmul(Wd, G.reshape(n, nq * 3, 9))                          # [n, b, r]
+
+        matm = (self.lam[elems], self.mu[elems], self.rho[elems])
+        for i in range(4):
+            kind = self.face_kind[elems, i]
+            scale = 2.0 * self.geo.area[elems, i] / self.geo.absdet[elems]
+            n = self.geo.normal[elems, i]
+            # ordinary faces at the (N+2)^2 flux points
+            Im = np.matmul(self.phi_f[i], I)
+            Ip = np.zeros_like(Im)
+            lp, mp, rp = (a.copy() for a in matm)
+            inter = np.nonzero((kind == FACE_INTERIOR) | (kind == FACE_PERIODIC))[0]
+            if inter.size:
+                J = self.nb[elems[inter], i]
+                Inb = self._integral(hist, J, t0, t0 + length)
+                Ip[inter] = np.matmul(self._neighbour_basis(c, i), Inb)
+                lp[inter], mp[inter], rp[inter] = self.lam[J], self.mu[J], self.rho[J]
+            for k in (FACE_ABSORBING, FACE_WALL, FACE_FREE):
+                sel = np.nonzero(kind == k)[0]
+                if sel.size:
+                    Ip[sel] = ghost_state(k, Im[sel])
+            nq = Im.shape[1]
+            nn = np.broadcast_to(n[:, None, :], (n.shape[0], nq, 3))
+            F = godunov_flux(Im, Ip, nn,
+                             tuple(m[:, None] * np.ones(nq) for m in matm),
+                             (lp[:, None] * np.ones(nq), mp[:, None] * np.ones(nq),
+                              rp[:, None] * np.ones(nq)))
+            F[kind == FACE_GRAVITY] = 0.0
+            dQ -= scale[:, None, None] * np.matmul((self.phi_f[i] * self.fw[:, None]).T, F)
+
+        # gravity faces of this cluster (Sec. 4.3)
+        gsel = np.nonzero(self.cluster[self.grav_elem] == c)[0]
+        if gsel.size:
+            ge = self.grav_elem[gsel]
+            gf = self.grav_face[gsel]
+            rows = self.pos[ge]
+            D = own[rows]                                   # [m, N+1, B, 9]
+            for i in range(4):
+                s2 = np.nonzero(gf == i)[0]
+                if not s2.size:
+                    continue
+                e = ge[s2]
+                Dq = ein("qb,nkbp->nkqp", self.phi_g[i], D[s2])  # [m, N+1, q, 9]
+                n = self.geo.normal[e, i]                    # [m, 3]
+                S = stress_tensor(Dq)
+                pm = -ein("ni,nkqij,nj->nkq", n, S, n)
+                vn = ein("ni,nkqi->nkq", n, Dq[..., 6:9])
+                Z = self.Zp[e][:, None, None]
+                Fm = np.moveaxis(vn + pm / Z, 1, 2)          # [m, q, N+1]
+                a = (self.rho[e] * self.g / self.Zp[e])[:, None]
+                eta0 = self.eta[gsel[s2]]
+                eta1, H = gravity_eta_step(eta0, Fm, a, dt)
+                # time-integrated boundary state: int v_n^b = eta1 - eta0, int p^b = rho g H
+                nq = eta0.shape[1]
+                nn = np.broadcast_to(n[:, None, :], (n.shape[0], nq, 3))
+                vb = (eta1 - eta0)[..., None] * nn
+                tb = -(self.rho[e][:, None] * self.g * H)[..., None] * nn
+                ones = np.ones(nq)
+                F = flux_of_state(self.lam[e][:, None] * ones, self.mu[e][:, None] * ones,
+                                  self.rho[e][:, None] * ones, nn, vb, tb)
+                scale = 2.0 * self.geo.area[e, i] / self.geo.absdet[e]
+                upd = scale[:, None, None] * ein("q,qb,nqp->nbp", self.gw, self.phi_g[i], F)
+                # elems is sorted; map each gravity face to its row in dQ
+                idx = np.searchsorted(elems, e)
+                np.subtract.at(dQ, idx, upd)
+                self.eta[gsel[s2]] = eta1
+        self.Q[elems] += dQ
+        self.updates += elems.size
+
+    # ------------------------------------------------------------------
+    def macro_step(self):
+        """One LTS macro step: 2^(C-1) sub-steps of dt_min (Sec. 4.4)."""
+        C = self.n_clusters
+        nsub = 1 << (C - 1)
+        hist = {c: [] for c in range(C)}
+        start = {c: 0 for c in range(C)}
+        for s in range(nsub):
+            for c in range(C):
+                if s % (1 << c) == 0 and self.members[c].size:
+                    hist[c].append((s, 1 << c, self.predict(self.members[c])))
+                    start[c] = s
+            for c in range(C):
+                if (s + 1) % (1 << c) == 0 and self.members[c].size:
+                    self.correct(c, hist, start[c])
+        self.time += nsub * self.dt_min
+
+    def run(self, n_macro: int):
+        for _ in range(n_macro):
+            self.macro_step()
+
+    # ------------------------------------------------------------------
+    def project(self, fn):
+        """L2 projection of q0(x) (fn: [n, 3] -> [n, 9]) onto the basis."""
+        x = self.geo.x0[:, None, :] + ein("edc,qc->eqd", self.geo.J, self.vpts)
+        vals = fn(x.reshape(-1, 3)).reshape(self.E, -1, 9)
+        return ein("q,qb,eqp->ebp", self.vw, self.phi_v, vals)
+
+    def eta_points(self):
+        """Physical points [F_g, q, 3] where eta is stored."""
+        return self.geo.face_points(self.grav_elem, self.grav_face, self.gst)
+
+    def energy(self, Q=None, eta=None):
+        """E = sum_K int_K (rho|v|^2/2 + W(s)) + sum_gravity faces int rho g eta^2 / 2."""
+        Q = self.Q if Q is None else Q
+        eta = self.eta if eta is None else eta
+        qv = ein("qb,ebp->eqp", self.phi_v, Q)
+        v2 = np.sum(qv[..., 6:9] ** 2, axis=-1)
+        S = stress_tensor(qv)
+        ss = ein("eqij,eqij->eq", S, S)
+        tr = ein("eqii->eq", S)
+        lam, mu = self.lam[:, None], self.mu[:, None]
+        ela = (mu > 0)
+        W_el = (ss - lam / (3 * lam + 2 * mu) * tr ** 2) / (4 * np.where(ela, mu, 1.0))
+        p = -tr / 3.0
+        W_ac = p ** 2 / (2 * lam)
+        W = np.where(ela, W_el, W_ac)
+        dens = 0.5 * self.rho[:, None] * v2 + W
+        E = float(np.sum(self.geo.absdet[:, None] * self.vw[None, :] * dens))
+        if self.grav_elem.size:
+            a2 = 2.0 * self.geo.area[self.grav_elem, self.grav_face]
+            E += float(np.sum(a2[:, None] * self.gw[None, :] * 0.5 * self.rho[self.grav_elem][:, None]
+                              * self.g * eta ** 2))
+        return E
+
+    def evaluate(self, x_elem, xi):
+        """Solution at reference points xi[n, 3] of elements x_elem[n] -> [n, 9]."""
+        phi = bas.eval_basis(self.N, xi)
+        return ein("nb,nbp->np", phi, self.Q[x_elem])
