@@ -1,0 +1,222 @@
+"""Throughput of the ADER-DG element update on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp64|bf16]
+                    [--kernel tuned|plain] [--order 6] [--scale 1] [--no-cpu-baseline]
+
+Workload: the graded, jittered ocean-over-solid box (72 x 72 x 64 cubes x 6 =
+1 990 656 tetrahedra; 500 m horizontal cells, vertical layers graded from
+500 m to 125 m toward the sea surface, top quarter water with a gravity
+surface), order 6 (B = 56), rate-2 LTS with up to 4 clusters. A step is one
+LTS macro step; the element updates of a macro step are sum_c n_c 2^(C-1-c).
+Inputs (mesh data, DOFs) are resident in HBM before the timed region.
+
+Prints one JSON line with the metric, a roofline object for the dominant
+kernel (event-timed on the library's stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp64_TF": 78.6,
+    "fp32_TF": 157.3,
+    "bf16_TF": 2500.0,
+}
+BYTES = {"fp64": 8, "fp32": 4, "bf16": 4}
+
+
+def nb(N):
+    return (N + 1) * (N + 2) * (N + 3) // 6
+
+
+def nf(N):
+    return (N + 1) * (N + 2) // 2
+
+
+def algorithmic_counts(N, value_bytes):
+    """Per-element algorithmic flops and HBM bytes of the predictor and corrector kernels.
+
+    Star matrices count with their 24 non-zeros, flux matrices dense 9x9,
+    face traces at Bf nodes per face.
+    """
+    B, Bf, B1 = nb(N), nf(N), nb(N - 1)
+    ck = sum(2 * 3 * nb(N - k - 1) * nb(N - k) * 9 + 2 * nb(N - k - 1) * 72 for k in range(N))
+    tint = sum(2 * nb(N - k) * 9 for k in range(N + 1))
+    traces = 2 * 4 * Bf * B * 9
+    flux = 2 * 4 * Bf * 81
+    volume = 2 * B1 * 72 + 2 * B * 3 * B1 * 9
+    lift = 2 * 4 * B * Bf * 9
+    pred_flops = ck + tint + traces + flux + volume + lift
+    corr_flops = flux + lift
+    vb = value_bytes
+    pred_bytes = vb * (B * 9 + 12 + 4 * 81 + 4 * Bf * 9 + B * 9)
+    corr_bytes = vb * (B * 9 + 4 * Bf * 9 + 4 * 81 + B * 9)
+    return dict(pred_flops=pred_flops, corr_flops=corr_flops, pred_bytes=pred_bytes, corr_bytes=corr_bytes)
+
+
+def workload(scale, seed=0):
+    from paper_2107_06640_amd import inputs
+    mesh, mats = inputs.cfg3(scale=scale, seed=seed)
+    return mesh, mats
+
+
+def tiled_dofs(E, B, seed, wet):
+    """Random DOFs for E elements by tiling a seeded block (throughput input)."""
+    from paper_2107_06640_amd import inputs
+    blk = min(E, 8192)
+    base = inputs.random_dofs(blk, B, seed=seed)
+    reps = -(-E // blk)
+    q = np.tile(base, (reps, 1, 1))[:E]
+    q[wet, :, 1] = q[wet, :, 0]
+    q[wet, :, 2] = q[wet, :, 0]
+    q[wet, :, 3:6] = 0.0
+    return q
+
+
+def cpu_baseline(order, budget_s=15.0):
+    """Oracle element-updates/s on a 6 x 6 x 8-cube sample of the workload (GTS)."""
+    from oracle.solver import Oracle
+    from paper_2107_06640_amd import inputs
+    zn = inputs.graded_z_nodes(8, 500.0, 250.0)
+    mesh, mats = inputs.coupled_box(6, 6, 8, cell=500.0, water_layers=2, z_nodes=zn, jitter=0.2, seed=0)
+    rho, lam, mu = mats
+    o = Oracle(mesh.xyz, mesh.tet, mesh.face_kind, mesh.period, rho, lam, mu, order - 1)
+    o.Q[:] = inputs.random_dofs(mesh.n_elements, o.B, seed=0, acoustic=mu == 0)
+    o.run(1)  # warm caches
+    t0 = time.perf_counter()
+    u0 = o.updates
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        o.run(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return dict(value=(o.updates - u0) / dt, unit="element-updates/s", cores=int(cores), kind="oracle",
+                sample=f"{mesh.n_elements} tets (6x6x8 cubes of the graded coupled box, order {order}, "
+                       f"global time stepping), {n} steps in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--kernel", default="tuned", choices=["tuned", "plain"])
+    ap.add_argument("--order", type=int, default=6)
+    ap.add_argument("--scale", type=int, default=1)
+    ap.add_argument("--max-clusters", type=int, default=4)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the method would shard by domain decomposition, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2107_06640_amd import seis
+
+    t_setup = time.perf_counter()
+    mesh, mats = workload(args.scale)
+    rho, lam, mu = mats
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    s = seis.from_mesh(mesh, mats, args.order, precision=args.precision, kernel=args.kernel,
+                       max_clusters=args.max_clusters, stream=stream.cuda_stream, tile=args.tile)
+    inf = s.info()
+    q = tiled_dofs(mesh.n_elements, inf["n_basis"], 0, mu == 0)
+    s.write(q)
+    del q
+    t_setup = time.perf_counter() - t_setup
+    print(f"# setup {t_setup:.1f} s, E={inf['n_elements']}, clusters={inf['cluster_size']}, "
+          f"updates/macro={inf['updates_per_macro_step']}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        s.step()
+    s.sync()
+    torch.cuda.synchronize()
+
+    s.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        s.step()
+    stop.record(stream)
+    stop.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    prof = s.profile_read()
+    s.profile(False)
+    upd = inf["updates_per_macro_step"] * args.steps
+    value = upd / (ms / 1e3)
+
+    N = args.order - 1
+    cnt = algorithmic_counts(N, BYTES[args.precision])
+    pms, pl, pe = prof["predict"]
+    cms, cl, ce = prof["correct"]
+    dom = "predict" if pms >= cms else "correct"
+    kms, kl, ke = prof[dom]
+    flops = cnt["pred_flops" if dom == "predict" else "corr_flops"] * ke / kl
+    byts = cnt["pred_bytes" if dom == "predict" else "corr_bytes"] * ke / kl
+    avg_s = kms / kl / 1e3
+    peak_tf = PEAK[{"fp64": "fp64_TF", "fp32": "fp32_TF", "bf16": "bf16_TF"}[args.precision]]
+    t_flop = flops / (peak_tf * 1e12)
+    t_byte = byts / (PEAK["hbm_GBs"] * 1e9)
+    if t_flop >= t_byte:
+        bound = "mfma" if args.kernel == "tuned" else "alu"
+        roof = dict(bound=bound, achieved=flops / avg_s / 1e12, peak=peak_tf, unit="TFLOP/s")
+    else:
+        roof = dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = kms / kl
+
+    out = {
+        "metric": "ADER-DG element-updates/s (order 6), FP32/BF16 vs FP64, % of roofline",
+        "value": value,
+        "unit": "element-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"graded jittered ocean-over-solid box, {inf['n_elements']} tets, "
+                               f"order {args.order} (B={inf['n_basis']}), rate-2 LTS {inf['n_clusters']} clusters "
+                               f"{inf['cluster_size']}, {inf['n_gravity_faces']} gravity faces",
+                   "kernel": args.kernel, "precision": args.precision, "elements": inf["n_elements"],
+                   "updates_per_step": inf["updates_per_macro_step"]},
+        "roofline": roof,
+        "kernels_ms": {k: v[0] for k, v in prof.items()},
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.order)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * seis.h -- C ABI of the MI355X element-update library for the ADER-DG
+ * discretisation of the coupled elastic-acoustic system with a gravity sea
+ * surface (Krenz et al., "3D Acoustic-Elastic Coupling with Gravity", SC'21).
+ *
+ * Problem (Sec. 3 and Sec. 4.1): q_t + A q_x + B q_y + C q_z = 0 for
+ * q = (s_xx, s_yy, s_zz, s_xy, s_yz, s_xz, v_x, v_y, v_z) on conforming
+ * tetrahedra with element-constant (rho, lambda, mu); mu = 0 elements are
+ * the acoustic ocean (s = -p I). Faces use the exact Godunov flux of the
+ * elastic-acoustic Riemann problem (Sec. 4.2); boundaries are imposed
+ * through ghost states (Sec. 4.3); the sea surface z = 0 carries the
+ * displacement eta through p' = rho g eta, d eta/dt = u_z (Sec. 3, gravity
+ * boundary condition; Sec. 4.3, coupled ODE). Elements are stepped with the
+ * ADER predictor-corrector (Sec. 4.1) and rate-2 clustered local time
+ * stepping (Sec. 4.4).
+ *
+ * Conventions fixed by this ABI
+ *   - Order O = N + 1 (convergence order); N is the polynomial degree, and
+ *     each element carries B = (N+1)(N+2)(N+3)/6 modal coefficients per
+ *     quantity (Sec. 4.1, basis dimension). Supported: 3 <= O <= 7.
+ *   - Basis: orthonormal Dubiner basis on the reference tetrahedron
+ *     {x,y,z >= 0, x+y+z <= 1} mapped by x = X0 + [X1-X0, X2-X0, X3-X0] xi from
+ *     the element's vertices in the caller's order (either orientation).
+ *     phi_pqr = P_p(a) ((1-b)/2)^p P_q^(2p+1,0)(b) ((1-c)/2)^(p+q) P_r^(2p+2q+2,0)(c),
+ *     a = 2x/(1-y-z) - 1, b = 2y/(1-z) - 1, c = 2z - 1, normalised to unit L2
+ *     norm on the reference element, ordered by (p+q+r, r, q, p).
+ *   - DOFs at the boundary: FP64 [E][B][9], caller's element order.
+ *   - Face i of an element is opposite its local vertex i, parametrised by
+ *     its vertices in ascending local order.
+ *   - eta: FP64 [F_g][(N+1)^2]. Gravity faces are ordered by (element,
+ *     local face); the points are the collapsed Gauss rule on the face,
+ *     s = (1+a_i)(1-b_j)/4, t = (1+b_j)/2 (a: Gauss-Legendre, b:
+ *     Gauss-Jacobi(1,0), N+1 points each), point index j*(N+1)+i.
+ *
+ * Errors: every int-returning call returns SEIS_OK (0) or a negative code;
+ * seis_last_error() gives the message. No call aborts or throws across the
+ * ABI. A handle is not thread-safe: serialise calls on one handle.
+ */
+#ifndef SEIS_H
+#define SEIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SEIS_OK = 0,
+  SEIS_EINVAL = -1,  /* bad argument, degenerate element, unmatched face, ... */
+  SEIS_ENOMEM = -2,  /* host or device allocation failed */
+  SEIS_EDEVICE = -3, /* HIP error (message kept) or no gfx950 device */
+  SEIS_EORDER = -4,  /* call out of schedule order (see seis_predict/seis_correct) */
+  SEIS_ERANGE = -5   /* cluster id or element id out of range */
+};
+
+/* Face kinds, face i opposite local vertex i. */
+enum {
+  SEIS_FACE_INTERIOR = 0,  /* matched by its three vertex ids */
+  SEIS_FACE_PERIODIC = 1,  /* matched by centroid modulo period[] */
+  SEIS_FACE_GRAVITY = 2,   /* sea surface z = 0 with gravity (Sec. 4.3); acoustic elements only */
+  SEIS_FACE_ABSORBING = 3, /* zero ghost state */
+  SEIS_FACE_WALL = 4,      /* rigid wall: ghost v+ = -v-, same stress */
+  SEIS_FACE_FREE = 5       /* traction-free surface (g = 0): ghost s+ = -s-, same velocity */
+};
+
+enum { SEIS_FP64 = 0, SEIS_FP32 = 1, SEIS_BF16 = 2 };
+enum { SEIS_KERNEL_TUNED = 0, SEIS_KERNEL_PLAIN = 1 };
+
+typedef struct seis_t seis_t; /* opaque; owns all device memory */
+
+/* Mesh description. All arrays are host memory owned by the caller and are
+ * copied during seis_setup. */
+typedef struct {
+  int64_t n_vertices;
+  const double *xyz;       /* [n_vertices][3], metres */
+  int64_t n_elements;
+  const int64_t *tet;      /* [n_elements][4] vertex ids, any orientation */
+  const int8_t *face_kind; /* [n_elements][4], SEIS_FACE_* */
+  double period[3];        /* periodic box lengths, 0 = not periodic */
+} seis_mesh_t;
+
+/* Per-element material (Sec. 3): density, Lame parameters; mu == 0 is acoustic. */
+typedef struct {
+  const double *rho;
+  const double *lambda;
+  const double *mu;
+} seis_materials_t;
+
+typedef struct {
+  int precision;    /* SEIS_FP64 / SEIS_FP32 / SEIS_BF16 (operands; FP32 accumulation) */
+  int kernel;       /* SEIS_KERNEL_TUNED (default) or SEIS_KERNEL_PLAIN */
+  double cfl;       /* C in dt_K = C/(2N+1) h_K / c_p,K (Sec. 4.4); default 0.35 */
+  double g;         /* gravitational acceleration (Sec. 3); default 9.81 */
+  int max_clusters; /* rate-2 LTS clusters (Sec. 4.4); 1 = global time stepping */
+  void *stream;     /* hipStream_t to launch on; NULL = the default stream */
+  int tile;         /* elements per work-group for the tuned kernels; 0 = autotuned default */
+} seis_options_t;
+
+typedef struct {
+  int order;            /* O = N + 1 */
+  int n_basis;          /* B */
+  int n_face_nodes;     /* (N+1)(N+2)/2 */
+  int n_eta_points;     /* (N+1)^2 */
+  int precision;
+  int kernel;
+  int n_clusters;
+  int64_t n_elements;
+  int64_t n_gravity_faces;
+  double dt_min;        /* smallest element time step; cluster c steps 2^c dt_min */
+  double time;          /* simulated time of the last completed macro step */
+  int64_t cluster_size[16];
+  int64_t updates_per_macro_step; /* sum_c n_c 2^(C-1-c) */
+  int64_t device_bytes;
+} seis_info_t;
+
+/* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream. */
+void seis_default_options(seis_options_t *opt);
+
+/* Build the solver for a mesh (Sec. 4.1-4.4): validate, match faces,
+ * assemble geometry, element Jacobians and the per-face Godunov flux
+ * matrices F-, F+ (Sec. 4.2, bilinear rewrite of the numerical flux) in FP64,
+ * assign LTS clusters, allocate device state (all zero: Q = 0, eta = 0).
+ * order: O = N + 1 in [3, 7]. opt may be NULL (defaults). On success *out
+ * owns the handle; free it with seis_destroy.
+ * Errors: SEIS_EINVAL (degenerate element, unmatched interior or periodic
+ * face, gravity face not acoustic or not horizontal with outward normal +z,
+ * more than one gravity face per element, bad order), SEIS_ENOMEM, SEIS_EDEVICE. */
+int seis_setup(const seis_mesh_t *mesh, const seis_materials_t *mat, int order,
+               const seis_options_t *opt, seis_t **out);
+
+/* Copy state from host FP64: dofs [E][B][9] (caller order) and/or eta
+ * [F_g][(N+1)^2]; either may be NULL to keep the current value. Resets the
+ * schedule to the start of a macro step. */
+int seis_write(seis_t *h, const double *dofs, const double *eta);
+
+/* ADER predictor of every element of cluster c for its next step (Sec. 4.1,
+ * Taylor expansion; Cauchy-Kowalevski procedure), its time integral, the
+ * element-local part of the corrector (volume term and local flux term of the
+ * semi-discrete form, Sec. 4.1 and 4.2) and the gravity surface faces of the
+ * cluster (per-point eta ODE and time-integrated boundary state, Sec. 4.3).
+ * It also hands each face neighbour the time-integrated trace it needs.
+ * Errors: SEIS_ERANGE (bad c), SEIS_EORDER (cluster c already predicted and
+ * not yet corrected). */
+int seis_predict(seis_t *h, int c);
+
+/* Neighbour flux term of the corrector for cluster c (Sec. 4.2, F+ q+ part),
+ * completing the step of cluster c; advances its time by 2^c dt_min.
+ * Errors: SEIS_ERANGE, SEIS_EORDER (c not predicted, or a neighbour cluster
+ * has not yet predicted the interval c needs). */
+int seis_correct(seis_t *h, int c);
+
+/* One LTS macro step (2^(C-1) sub-steps of dt_min): in sub-step s the
+ * predictors of the clusters with s mod 2^c == 0, then the correctors of the
+ * clusters with (s+1) mod 2^c == 0 (Sec. 4.4). Launches asynchronously on the
+ * handle's stream. */
+int seis_step(seis_t *h);
+
+/* Run n macro steps (same as calling seis_step n times). */
+int seis_run(seis_t *h, int n);
+
+/* Copy state to host FP64 (synchronises the stream first): dofs [E][B][9]
+ * in caller element order and/or eta [F_g][(N+1)^2]; either may be NULL.
+ * Errors: SEIS_EORDER if a cluster is between predict and correct. */
+int seis_read(seis_t *h, double *dofs, double *eta);
+
+/* Read only the DOFs of n elements (caller ids) into dofs [n][B][9]. */
+int seis_read_elements(seis_t *h, const int64_t *ids, int64_t n, double *dofs);
+
+/* Summary of the handle (sizes, clusters, time step). */
+int seis_info(const seis_t *h, seis_info_t *info);
+
+/* Cluster of every element, caller order: out [E]. */
+int seis_cluster_of(const seis_t *h, int32_t *out);
+
+/* Per-kernel timing for measurement: with enable != 0 every kernel launch of
+ * the handle is bracketed by HIP events on the handle's stream and the
+ * totals are cleared; enable == 0 stops recording. */
+int seis_profile(seis_t *h, int enable);
+
+/* Totals since profiling was enabled, for the kernel kinds
+ * [0] predictor, [1] gravity face, [2] corrector: elapsed ms, number of
+ * launches and number of elements (gravity: faces) processed. Any pointer may
+ * be NULL. Synchronises the stream. */
+int seis_profile_read(seis_t *h, double *ms, int64_t *launches, int64_t *elements);
+
+/* Synchronise the handle's stream. */
+int seis_sync(seis_t *h);
+
+/* Free all memory of the handle (NULL is ignored). */
+void seis_destroy(seis_t *h);
+
+/* Message of the last error on this handle (or of the last failed
+ * seis_setup when h is NULL). Never NULL. */
+const char *seis_last_error(const seis_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEIS_H */

@@ -1,0 +1,601 @@
+// C ABI of the library (see include/seis.h): handle, device buffers,
+// schedule bookkeeping and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/seis.h"
+#include "device.hpp"
+#include "model.hpp"
+#include "tuned.hpp"
+
+using namespace seis;
+
+namespace {
+
+std::mutex g_err_mu;
+std::string g_setup_error = "no error";
+
+struct Buffers {
+  std::vector<void*> ptrs;
+  int64_t bytes = 0;
+  template <typename X>
+  hipError_t alloc(X** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    void* q = nullptr;
+    hipError_t st = hipMalloc(&q, n * sizeof(X));
+    if (st != hipSuccess) return st;
+    ptrs.push_back(q);
+    bytes += int64_t(n * sizeof(X));
+    *p = static_cast<X*>(q);
+    return hipSuccess;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+}  // namespace
+
+struct seis_t {
+  Model M;
+  int precision = SEIS_FP64;
+  int kernel = SEIS_KERNEL_TUNED;
+  int tile = 0;
+  hipStream_t stream = nullptr;
+  Buffers buf;
+  DevData<double> d64{};
+  DevData<float> d32{};
+  TunedData tuned{};
+  int32_t* glist = nullptr;             // gravity faces grouped by cluster
+  std::vector<int64_t> gstart;          // [C+1]
+  std::string err = "no error";
+  // schedule cursor inside the current macro step
+  int sub = 0;                          // sub-step index
+  std::vector<int> predicted;           // per cluster, predicted in this sub-step
+  std::vector<int> corrected;
+  int64_t macro_done = 0;
+  // per-kernel event timing
+  bool prof = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { int kind; hipEvent_t a, b; int64_t n; };
+  std::vector<Rec> recs;
+  double tot_ms[3] = {0, 0, 0};
+  int64_t tot_launch[3] = {0, 0, 0}, tot_elem[3] = {0, 0, 0};
+};
+
+namespace {
+
+int fail(seis_t* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int hip_fail(seis_t* h, hipError_t st, const char* where) {
+  return fail(h, SEIS_EDEVICE, std::string(where) + ": " + hipGetErrorString(st));
+}
+
+#define HIPCHK(h, call, where)                      \
+  do {                                              \
+    hipError_t _st = (call);                        \
+    if (_st != hipSuccess) return hip_fail(h, _st, where); \
+  } while (0)
+
+template <typename X, typename Y>
+hipError_t upload(Buffers& b, X** dst, const std::vector<Y>& src) {
+  hipError_t st = b.alloc(dst, src.size());
+  if (st != hipSuccess) return st;
+  if (src.empty()) return hipSuccess;
+  std::vector<X> tmp(src.begin(), src.end());
+  return hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(X), hipMemcpyHostToDevice);
+}
+
+bool due_predict(int s, int c) { return (s % (1 << c)) == 0; }
+bool due_correct(int s, int c) { return ((s + 1) % (1 << c)) == 0; }
+
+template <typename T>
+int build_dev(seis_t* h, DevData<T>& d) {
+  Model& M = h->M;
+  Buffers& b = h->buf;
+  const int64_t E = M.E;
+  const int B = M.B, Bf = M.Bf, N = M.N;
+  d.E = E;
+  d.g = M.g;
+  T *Q, *G, *mat, *Fm, *Fp, *In, *H2, *gD, *K, *Ef, *Lf;
+  HIPCHK(h, b.alloc(&Q, E * B * 9), "alloc Q");
+  HIPCHK(h, hipMemset(Q, 0, E * B * 9 * sizeof(T)), "memset Q");
+  HIPCHK(h, upload(b, &G, M.G), "upload G");
+  HIPCHK(h, upload(b, &mat, M.mat), "upload mat");
+  HIPCHK(h, upload(b, &Fm, M.Fm), "upload Fm");
+  HIPCHK(h, upload(b, &Fp, M.Fp), "upload Fp");
+  HIPCHK(h, b.alloc(&In, E * 4 * Bf * 9), "alloc In");
+  HIPCHK(h, hipMemset(In, 0, E * 4 * Bf * 9 * sizeof(T)), "memset In");
+  HIPCHK(h, b.alloc(&H2, std::max<int64_t>(M.n_half2, 1) * Bf * 9), "alloc H2");
+  HIPCHK(h, hipMemset(H2, 0, std::max<int64_t>(M.n_half2, 1) * Bf * 9 * sizeof(T)), "memset H2");
+  const int64_t Fg = (int64_t)M.g_elem.size();
+  HIPCHK(h, b.alloc(&gD, std::max<int64_t>(Fg, 1) * (N + 1) * B * 9), "alloc gD");
+  HIPCHK(h, upload(b, &K, M.ref.K), "upload K");
+  HIPCHK(h, upload(b, &Ef, M.ref.E), "upload E");
+  HIPCHK(h, upload(b, &Lf, M.ref.L), "upload L");
+  d.Q = Q; d.G = G; d.mat = mat; d.Fm = Fm; d.Fp = Fp; d.In = In; d.H2 = H2; d.gD = gD;
+  d.K = K; d.Ef = Ef; d.Lf = Lf;
+  return SEIS_OK;
+}
+
+template <typename T>
+void share_common(const DevData<double>& c, DevData<T>& d) {
+  d.tgt = c.tgt; d.mode = c.mode; d.hperm = c.hperm; d.half2 = c.half2; d.rhalf2 = c.rhalf2;
+  d.gslot = c.gslot; d.perm = c.perm; d.Eg = c.Eg; d.Lg = c.Lg; d.g_elem = c.g_elem; d.g_face = c.g_face;
+  d.g_par = c.g_par; d.eta = c.eta;
+}
+
+int build_common(seis_t* h, DevData<double>& c) {
+  Model& M = h->M;
+  Buffers& b = h->buf;
+  int32_t *tgt, *half2, *rhalf2, *gslot, *perm, *gelem;
+  int8_t *mode, *hperm, *gface;
+  double *Eg, *Lg, *gpar, *eta;
+  HIPCHK(h, upload(b, &tgt, M.tgt), "upload tgt");
+  HIPCHK(h, upload(b, &mode, M.mode), "upload mode");
+  HIPCHK(h, upload(b, &hperm, M.hperm), "upload hperm");
+  HIPCHK(h, upload(b, &half2, M.half2), "upload half2");
+  HIPCHK(h, upload(b, &rhalf2, M.rhalf2), "upload rhalf2");
+  HIPCHK(h, upload(b, &gslot, M.gslot), "upload gslot");
+  HIPCHK(h, upload(b, &perm, M.ref.perm), "upload perm");
+  HIPCHK(h, upload(b, &Eg, M.ref.Eg), "upload Eg");
+  HIPCHK(h, upload(b, &Lg, M.ref.Lg), "upload Lg");
+  std::vector<int32_t> ge(M.g_elem.begin(), M.g_elem.end());
+  HIPCHK(h, upload(b, &gelem, ge), "upload g_elem");
+  HIPCHK(h, upload(b, &gface, M.g_face), "upload g_face");
+  HIPCHK(h, upload(b, &gpar, M.g_par), "upload g_par");
+  const int64_t Fg = (int64_t)M.g_elem.size();
+  HIPCHK(h, b.alloc(&eta, std::max<int64_t>(Fg, 1) * M.nq), "alloc eta");
+  HIPCHK(h, hipMemset(eta, 0, std::max<int64_t>(Fg, 1) * M.nq * sizeof(double)), "memset eta");
+  // gravity faces grouped by cluster
+  std::vector<int32_t> gl;
+  h->gstart.assign(M.C + 1, 0);
+  for (int cc = 0; cc < M.C; ++cc) {
+    h->gstart[cc] = (int64_t)gl.size();
+    for (int64_t f = 0; f < Fg; ++f) {
+      const int64_t e = M.g_elem[f];
+      if (e >= M.cluster_start[cc] && e < M.cluster_start[cc + 1]) gl.push_back(int32_t(f));
+    }
+  }
+  h->gstart[M.C] = (int64_t)gl.size();
+  HIPCHK(h, upload(b, &h->glist, gl), "upload glist");
+  c.tgt = tgt; c.mode = mode; c.hperm = hperm; c.half2 = half2; c.rhalf2 = rhalf2; c.gslot = gslot;
+  c.perm = perm; c.Eg = Eg; c.Lg = Lg; c.g_elem = gelem; c.g_face = gface; c.g_par = gpar; c.eta = eta;
+  c.g = M.g;
+  return SEIS_OK;
+}
+
+hipEvent_t next_event(seis_t* h) {
+  if (h->used == h->pool.size()) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    h->pool.push_back(ev);
+  }
+  return h->pool[h->used++];
+}
+
+// fold recorded event pairs into the totals
+hipError_t fold_profile(seis_t* h) {
+  if (h->recs.empty()) return hipSuccess;
+  hipError_t st = hipEventSynchronize(h->recs.back().b);
+  if (st != hipSuccess) return st;
+  for (auto& r : h->recs) {
+    float ms = 0.0f;
+    st = hipEventElapsedTime(&ms, r.a, r.b);
+    if (st != hipSuccess) return st;
+    h->tot_ms[r.kind] += ms;
+    h->tot_launch[r.kind] += 1;
+    h->tot_elem[r.kind] += r.n;
+  }
+  h->recs.clear();
+  h->used = 0;
+  return hipSuccess;
+}
+
+// launch fn() bracketed by events when profiling
+template <typename F>
+hipError_t timed(seis_t* h, int kind, int64_t n, F fn) {
+  if (!h->prof || n <= 0) return fn();
+  if (h->used + 2 > 4096) {
+    hipError_t st = fold_profile(h);
+    if (st != hipSuccess) return st;
+  }
+  hipEvent_t a = next_event(h), b = next_event(h);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t st = hipEventRecord(a, h->stream);
+  if (st != hipSuccess) return st;
+  st = fn();
+  if (st != hipSuccess) return st;
+  st = hipEventRecord(b, h->stream);
+  if (st != hipSuccess) return st;
+  h->recs.push_back({kind, a, b, n});
+  return hipSuccess;
+}
+
+int do_predict(seis_t* h, int c) {
+  Model& M = h->M;
+  const int64_t e0 = M.cluster_start[c], ne = M.cluster_start[c + 1] - e0;
+  const int parity = (h->sub >> c) & 1;
+  hipError_t st = hipSuccess;
+  const int32_t* gl = h->glist + h->gstart[c];
+  const int64_t ng = h->gstart[c + 1] - h->gstart[c];
+  const int N = M.N;
+  st = timed(h, 0, ne, [&]() -> hipError_t {
+    if (h->kernel == SEIS_KERNEL_PLAIN) {
+      if (h->precision == SEIS_FP64) return launch_predict_plain<double>(N, h->d64, e0, ne, parity, h->stream);
+      return launch_predict_plain<float>(N, h->d32, e0, ne, parity, h->stream);
+    }
+    return tuned_predict(h->tuned, h->precision, N, e0, ne, parity, h->stream);
+  });
+  if (st == hipSuccess)
+    st = timed(h, 1, ng, [&]() -> hipError_t {
+      if (h->precision == SEIS_FP64) return launch_gravity<double>(N, h->d64, gl, ng, h->stream);
+      return launch_gravity<float>(N, h->d32, gl, ng, h->stream);
+    });
+  if (st != hipSuccess) return hip_fail(h, st, "predict launch");
+  return SEIS_OK;
+}
+
+int do_correct(seis_t* h, int c) {
+  Model& M = h->M;
+  const int64_t e0 = M.cluster_start[c], ne = M.cluster_start[c + 1] - e0;
+  const int parity = (h->sub >> c) & 1;
+  const int N = M.N;
+  hipError_t st = timed(h, 2, ne, [&]() -> hipError_t {
+    if (h->kernel == SEIS_KERNEL_PLAIN) {
+      if (h->precision == SEIS_FP64) return launch_correct_plain<double>(N, h->d64, e0, ne, parity, h->stream);
+      return launch_correct_plain<float>(N, h->d32, e0, ne, parity, h->stream);
+    }
+    return tuned_correct(h->tuned, h->precision, N, e0, ne, parity, h->stream);
+  });
+  if (st != hipSuccess) return hip_fail(h, st, "correct launch");
+  return SEIS_OK;
+}
+
+void reset_cursor(seis_t* h) {
+  h->sub = 0;
+  h->predicted.assign(h->M.C, 0);
+  h->corrected.assign(h->M.C, 0);
+}
+
+bool mid_step(const seis_t* h) {
+  if (h->sub != 0) return true;
+  for (int c = 0; c < h->M.C; ++c)
+    if (h->predicted[c]) return true;
+  return false;
+}
+
+// advance the cursor once every due predict and correct of the sub-step ran
+void maybe_advance(seis_t* h) {
+  const int C = h->M.C;
+  for (int c = 0; c < C; ++c) {
+    if (h->M.cluster_start[c + 1] == h->M.cluster_start[c]) continue;
+    if (due_predict(h->sub, c) && !h->predicted[c]) return;
+    if (due_correct(h->sub, c) && !h->corrected[c]) return;
+  }
+  for (int c = 0; c < C; ++c) {
+    if (due_correct(h->sub, c)) {
+      h->predicted[c] = 0;
+      h->corrected[c] = 0;
+    }
+  }
+  h->sub++;
+  if (h->sub == (1 << (C - 1))) {
+    h->sub = 0;
+    h->macro_done++;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void seis_default_options(seis_options_t* o) {
+  if (!o) return;
+  o->precision = SEIS_FP64;
+  o->kernel = SEIS_KERNEL_TUNED;
+  o->cfl = 0.35;
+  o->g = 9.81;
+  o->max_clusters = 1;
+  o->stream = nullptr;
+  o->tile = 0;
+}
+
+int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, const seis_options_t* opt,
+               seis_t** out) {
+  auto setup_fail = [&](int code, const std::string& msg) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_setup_error = msg;
+    return code;
+  };
+  if (!out) return setup_fail(SEIS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mesh || !mat) return setup_fail(SEIS_EINVAL, "mesh or materials is NULL");
+  seis_options_t o;
+  seis_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision < SEIS_FP64 || o.precision > SEIS_BF16) return setup_fail(SEIS_EINVAL, "bad precision");
+  if (o.kernel != SEIS_KERNEL_TUNED && o.kernel != SEIS_KERNEL_PLAIN) return setup_fail(SEIS_EINVAL, "bad kernel");
+  if (o.kernel == SEIS_KERNEL_PLAIN && o.precision == SEIS_BF16)
+    return setup_fail(SEIS_EINVAL, "BF16 operands need the tuned (MFMA) kernels");
+  if (order < 3 || order > 7) return setup_fail(SEIS_EINVAL, "order must be in 3..7");
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return setup_fail(SEIS_EDEVICE, "no HIP device");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return setup_fail(SEIS_EDEVICE, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+  seis_t* h = new (std::nothrow) seis_t();
+  if (!h) return setup_fail(SEIS_ENOMEM, "host allocation failed");
+  std::string e;
+  try {
+    e = build_model(mesh->n_vertices, mesh->xyz, mesh->n_elements, mesh->tet, mesh->face_kind, mesh->period,
+                    mat->rho, mat->lambda, mat->mu, order - 1, o.cfl, o.g, o.max_clusters, h->M);
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return setup_fail(SEIS_ENOMEM, "host allocation failed during set-up");
+  } catch (const std::exception& ex) {
+    delete h;
+    return setup_fail(SEIS_EINVAL, ex.what());
+  }
+  if (!e.empty()) {
+    delete h;
+    return setup_fail(SEIS_EINVAL, e);
+  }
+  h->precision = o.precision;
+  h->kernel = o.kernel;
+  h->tile = o.tile;
+  h->stream = (hipStream_t)o.stream;
+  int rc = build_common(h, h->d64);
+  if (rc == SEIS_OK) {
+    if (o.precision == SEIS_FP64) {
+      rc = build_dev<double>(h, h->d64);
+    } else {
+      share_common(h->d64, h->d32);
+      rc = build_dev<float>(h, h->d32);
+    }
+  }
+  if (rc == SEIS_OK && o.kernel == SEIS_KERNEL_TUNED) {
+    hipError_t st = tuned_build(h->tuned, h->M, h->precision, h->d64, h->d32, h->tile, h->buf.ptrs, h->buf.bytes);
+    if (st != hipSuccess) rc = hip_fail(h, st, "tuned set-up");
+  }
+  if (rc == SEIS_OK) {
+    hipError_t st = hipDeviceSynchronize();
+    if (st != hipSuccess) rc = hip_fail(h, st, "set-up sync");
+  }
+  if (rc != SEIS_OK) {
+    const std::string msg = h->err;
+    h->buf.release();
+    delete h;
+    return setup_fail(rc, msg);
+  }
+  reset_cursor(h);
+  *out = h;
+  return SEIS_OK;
+}
+
+int seis_write(seis_t* h, const double* dofs, const double* eta) {
+  if (!h) return SEIS_EINVAL;
+  Model& M = h->M;
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  if (dofs) {
+    const int64_t n = M.E * M.B * 9;
+    const size_t row = (size_t)M.B * 9;
+    if (h->precision == SEIS_FP64) {
+      std::vector<double> tmp(n);
+      for (int64_t k = 0; k < M.E; ++k)
+        std::memcpy(&tmp[k * row], dofs + M.old_of_new[k] * row, row * sizeof(double));
+      HIPCHK(h, hipMemcpy(h->d64.Q, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice), "write Q");
+    } else {
+      std::vector<float> tmp(n);
+      for (int64_t k = 0; k < M.E; ++k) {
+        const double* src = dofs + M.old_of_new[k] * row;
+        for (size_t i = 0; i < row; ++i) tmp[k * row + i] = (float)src[i];
+      }
+      HIPCHK(h, hipMemcpy(h->d32.Q, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice), "write Q");
+    }
+  }
+  if (eta && !M.g_elem.empty()) {
+    HIPCHK(h, hipMemcpy(h->d64.eta, eta, M.g_elem.size() * M.nq * sizeof(double), hipMemcpyHostToDevice),
+           "write eta");
+  }
+  reset_cursor(h);
+  return SEIS_OK;
+}
+
+int seis_predict(seis_t* h, int c) {
+  if (!h) return SEIS_EINVAL;
+  if (c < 0 || c >= h->M.C) return fail(h, SEIS_ERANGE, "cluster id out of range");
+  if (!due_predict(h->sub, c) || h->predicted[c])
+    return fail(h, SEIS_EORDER, "cluster is not due for a prediction at this point of the LTS schedule");
+  int rc = do_predict(h, c);
+  if (rc != SEIS_OK) return rc;
+  h->predicted[c] = 1;
+  maybe_advance(h);
+  return SEIS_OK;
+}
+
+int seis_correct(seis_t* h, int c) {
+  if (!h) return SEIS_EINVAL;
+  const int C = h->M.C;
+  if (c < 0 || c >= C) return fail(h, SEIS_ERANGE, "cluster id out of range");
+  if (!due_correct(h->sub, c) || h->corrected[c])
+    return fail(h, SEIS_EORDER, "cluster is not due for a correction at this point of the LTS schedule");
+  for (int cc = 0; cc < C; ++cc)
+    if (h->M.cluster_start[cc + 1] > h->M.cluster_start[cc] && due_predict(h->sub, cc) && !h->predicted[cc])
+      return fail(h, SEIS_EORDER, "all predictions of the sub-step must run before its corrections");
+  if (!h->predicted[c]) return fail(h, SEIS_EORDER, "cluster has not been predicted for this step");
+  int rc = do_correct(h, c);
+  if (rc != SEIS_OK) return rc;
+  h->corrected[c] = 1;
+  maybe_advance(h);
+  return SEIS_OK;
+}
+
+int seis_step(seis_t* h) {
+  if (!h) return SEIS_EINVAL;
+  if (mid_step(h)) return fail(h, SEIS_EORDER, "a macro step is in progress; finish it with seis_predict/seis_correct");
+  const int C = h->M.C;
+  for (int s = 0; s < (1 << (C - 1)); ++s) {
+    for (int c = 0; c < C; ++c)
+      if (due_predict(s, c)) {
+        int rc = seis_predict(h, c);
+        if (rc) return rc;
+      }
+    for (int c = 0; c < C; ++c)
+      if (due_correct(s, c)) {
+        int rc = seis_correct(h, c);
+        if (rc) return rc;
+      }
+  }
+  return SEIS_OK;
+}
+
+int seis_run(seis_t* h, int n) {
+  for (int i = 0; i < n; ++i) {
+    int rc = seis_step(h);
+    if (rc) return rc;
+  }
+  return SEIS_OK;
+}
+
+int seis_read(seis_t* h, double* dofs, double* eta) {
+  if (!h) return SEIS_EINVAL;
+  if (mid_step(h)) return fail(h, SEIS_EORDER, "state is between a prediction and its correction");
+  Model& M = h->M;
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  if (dofs) {
+    const int64_t n = M.E * M.B * 9;
+    const size_t row = (size_t)M.B * 9;
+    if (h->precision == SEIS_FP64) {
+      std::vector<double> tmp(n);
+      HIPCHK(h, hipMemcpy(tmp.data(), h->d64.Q, n * sizeof(double), hipMemcpyDeviceToHost), "read Q");
+      for (int64_t k = 0; k < M.E; ++k)
+        std::memcpy(dofs + M.old_of_new[k] * row, &tmp[k * row], row * sizeof(double));
+    } else {
+      std::vector<float> tmp(n);
+      HIPCHK(h, hipMemcpy(tmp.data(), h->d32.Q, n * sizeof(float), hipMemcpyDeviceToHost), "read Q");
+      for (int64_t k = 0; k < M.E; ++k) {
+        double* dst = dofs + M.old_of_new[k] * row;
+        for (size_t i = 0; i < row; ++i) dst[i] = tmp[k * row + i];
+      }
+    }
+  }
+  if (eta && !M.g_elem.empty()) {
+    HIPCHK(h, hipMemcpy(eta, h->d64.eta, M.g_elem.size() * M.nq * sizeof(double), hipMemcpyDeviceToHost),
+           "read eta");
+  }
+  return SEIS_OK;
+}
+
+int seis_read_elements(seis_t* h, const int64_t* ids, int64_t n, double* dofs) {
+  if (!h || (!ids && n > 0) || (!dofs && n > 0) || n < 0) return SEIS_EINVAL;
+  if (mid_step(h)) return fail(h, SEIS_EORDER, "state is between a prediction and its correction");
+  Model& M = h->M;
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  const size_t row = (size_t)M.B * 9;
+  for (int64_t i = 0; i < n; ++i) {
+    if (ids[i] < 0 || ids[i] >= M.E) return fail(h, SEIS_ERANGE, "element id out of range");
+    const int64_t k = M.new_of_old[ids[i]];
+    if (h->precision == SEIS_FP64) {
+      HIPCHK(h, hipMemcpy(dofs + i * row, h->d64.Q + k * row, row * sizeof(double), hipMemcpyDeviceToHost),
+             "read element");
+    } else {
+      std::vector<float> tmp(row);
+      HIPCHK(h, hipMemcpy(tmp.data(), h->d32.Q + k * row, row * sizeof(float), hipMemcpyDeviceToHost),
+             "read element");
+      for (size_t j = 0; j < row; ++j) dofs[i * row + j] = tmp[j];
+    }
+  }
+  return SEIS_OK;
+}
+
+int seis_info(const seis_t* h, seis_info_t* info) {
+  if (!h || !info) return SEIS_EINVAL;
+  const Model& M = h->M;
+  std::memset(info, 0, sizeof(*info));
+  info->order = M.N + 1;
+  info->n_basis = M.B;
+  info->n_face_nodes = M.Bf;
+  info->n_eta_points = M.nq;
+  info->precision = h->precision;
+  info->kernel = h->kernel;
+  info->n_clusters = M.C;
+  info->n_elements = M.E;
+  info->n_gravity_faces = (int64_t)M.g_elem.size();
+  info->dt_min = M.dt_min;
+  info->time = double(h->macro_done) * double(1 << (M.C - 1)) * M.dt_min;
+  int64_t upd = 0;
+  for (int c = 0; c < M.C && c < 16; ++c) {
+    info->cluster_size[c] = M.cluster_start[c + 1] - M.cluster_start[c];
+    upd += info->cluster_size[c] << (M.C - 1 - c);
+  }
+  info->updates_per_macro_step = upd;
+  info->device_bytes = h->buf.bytes;
+  return SEIS_OK;
+}
+
+int seis_cluster_of(const seis_t* h, int32_t* out) {
+  if (!h || !out) return SEIS_EINVAL;
+  std::memcpy(out, h->M.cluster_old.data(), h->M.E * sizeof(int32_t));
+  return SEIS_OK;
+}
+
+int seis_profile(seis_t* h, int enable) {
+  if (!h) return SEIS_EINVAL;
+  HIPCHK(h, fold_profile(h), "profile");
+  for (int k = 0; k < 3; ++k) {
+    if (enable) {
+      h->tot_ms[k] = 0.0;
+      h->tot_launch[k] = 0;
+      h->tot_elem[k] = 0;
+    }
+  }
+  h->prof = enable != 0;
+  return SEIS_OK;
+}
+
+int seis_profile_read(seis_t* h, double* ms, int64_t* launches, int64_t* elements) {
+  if (!h) return SEIS_EINVAL;
+  HIPCHK(h, fold_profile(h), "profile");
+  for (int k = 0; k < 3; ++k) {
+    if (ms) ms[k] = h->tot_ms[k];
+    if (launches) launches[k] = h->tot_launch[k];
+    if (elements) elements[k] = h->tot_elem[k];
+  }
+  return SEIS_OK;
+}
+
+int seis_sync(seis_t* h) {
+  if (!h) return SEIS_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  return SEIS_OK;
+}
+
+void seis_destroy(seis_t* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t ev : h->pool) (void)hipEventDestroy(ev);
+  h->buf.release();
+  delete h;
+}
+
+const char* seis_last_error(const seis_t* h) {
+  if (h) return h->err.c_str();
+  std::lock_guard<std::mutex> lk(g_err_mu);
+  return g_setup_error.c_str();
+}
+
+}  // extern "C"

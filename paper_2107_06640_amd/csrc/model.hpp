@@ -1,0 +1,61 @@
+// Host-side model of a mesh after set-up (FP64), in the library's element
+// order: elements are grouped by LTS cluster (cluster c occupies
+// [cluster_start[c], cluster_start[c+1])), keeping the caller's relative
+// order inside a cluster.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "refelem.hpp"
+
+namespace seis {
+
+// Face exchange modes of the writer side (see the predictor kernels).
+enum FaceMode : int8_t {
+  MODE_NONE = 0,     // physical boundary: nothing is handed over
+  MODE_SAME = 1,     // neighbour in the same cluster: full-step integral
+  MODE_FINER = 2,    // neighbour one cluster finer: first and second half-step integrals
+  MODE_COARSER = 3,  // neighbour one cluster coarser: half of the integral, accumulated over two steps
+};
+
+struct Model {
+  int N = 0, B = 0, Bf = 0, nq = 0;
+  int64_t E = 0;
+  int C = 1;                           // number of clusters
+  double dt_min = 0.0;
+  std::vector<double> dt_c;            // [C]
+  std::vector<int64_t> cluster_start;  // [C+1]
+  std::vector<int64_t> new_of_old;     // [E]
+  std::vector<int64_t> old_of_new;     // [E]
+  std::vector<int32_t> cluster_old;    // [E], caller order
+
+  // per element (library order)
+  std::vector<double> G;               // [E][9] dt_c * Jinv, row d, column e: d xi_d / d x_e
+  std::vector<double> mat;             // [E][3] lambda, mu, 1/rho
+  std::vector<double> Fm, Fp;          // [E][4][81] scaled flux matrices (row p, column r)
+  std::vector<int32_t> tgt;            // [E][4] writer: K*4 + i of the receiving face, -1 none
+  std::vector<int8_t> mode;            // [E][4] writer FaceMode
+  std::vector<int8_t> hperm;           // [E][4] writer node map index (0..5)
+  std::vector<int32_t> half2;          // [E][4] writer MODE_FINER: slot of the second half
+  std::vector<int32_t> rhalf2;         // [E][4] reader: slot read on odd sub-steps, -1 none
+  int64_t n_half2 = 0;
+
+  // gravity faces (library element order of their elements, sorted by caller (element, face))
+  std::vector<int64_t> g_elem;         // [F_g] library element id
+  std::vector<int8_t> g_face;          // [F_g]
+  std::vector<double> g_par;           // [F_g][8]: scale 2A/|J|, n_x, n_y, n_z, Z, a = rho g / Z, lambda, dt
+  std::vector<int32_t> gslot;          // [E] gravity face index of an element, -1 none
+  std::vector<int64_t> g_order;        // [F_g]: ABI position of library gravity face f
+  double g = 9.81;
+
+  RefElement ref;
+};
+
+// Build the model. Returns an empty string on success, else an error message.
+std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t* tet, const int8_t* face_kind,
+                        const double period[3], const double* rho, const double* lam, const double* mu, int N,
+                        double cfl, double g, int max_clusters, Model& M);
+
+}  // namespace seis
