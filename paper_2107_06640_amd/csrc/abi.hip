@@ -11,6 +11,7 @@
 
 #include "../../include/seis.h"
 #include "device.hpp"
+#include "layout.hpp"
 #include "model.hpp"
 #include "tuned.hpp"
 
@@ -110,14 +111,15 @@ int build_dev(seis_t* h, DevData<T>& d) {
   d.E = E;
   d.g = M.g;
   T *Q, *G, *mat, *Fm, *Fp, *In, *H2, *gD, *K, *Ef, *Lf;
-  HIPCHK(h, b.alloc(&Q, E * B * 9), "alloc Q");
-  HIPCHK(h, hipMemset(Q, 0, E * B * 9 * sizeof(T)), "memset Q");
+  const int RT = row_tiles(B), FT = row_tiles(Bf);
+  HIPCHK(h, b.alloc(&Q, q_size(E, RT)), "alloc Q");
+  HIPCHK(h, hipMemset(Q, 0, q_size(E, RT) * sizeof(T)), "memset Q");
   HIPCHK(h, upload(b, &G, M.G), "upload G");
   HIPCHK(h, upload(b, &mat, M.mat), "upload mat");
   HIPCHK(h, upload(b, &Fm, M.Fm), "upload Fm");
   HIPCHK(h, upload(b, &Fp, M.Fp), "upload Fp");
-  HIPCHK(h, b.alloc(&In, E * 4 * Bf * 9), "alloc In");
-  HIPCHK(h, hipMemset(In, 0, E * 4 * Bf * 9 * sizeof(T)), "memset In");
+  HIPCHK(h, b.alloc(&In, in_size(E, FT)), "alloc In");
+  HIPCHK(h, hipMemset(In, 0, in_size(E, FT) * sizeof(T)), "memset In");
   HIPCHK(h, b.alloc(&H2, std::max<int64_t>(M.n_half2, 1) * Bf * 9), "alloc H2");
   HIPCHK(h, hipMemset(H2, 0, std::max<int64_t>(M.n_half2, 1) * Bf * 9 * sizeof(T)), "memset H2");
   const int64_t Fg = (int64_t)M.g_elem.size();
@@ -237,7 +239,7 @@ int do_predict(seis_t* h, int c) {
       if (h->precision == SEIS_FP64) return launch_predict_plain<double>(N, h->d64, e0, ne, parity, h->stream);
       return launch_predict_plain<float>(N, h->d32, e0, ne, parity, h->stream);
     }
-    return tuned_predict(h->tuned, h->precision, N, e0, ne, parity, h->stream);
+    return tuned_predict(h->tuned, h->precision, N, e0, M.iface_start[c], e0 + ne, parity, h->stream);
   });
   if (st == hipSuccess)
     st = timed(h, 1, ng, [&]() -> hipError_t {
@@ -258,7 +260,7 @@ int do_correct(seis_t* h, int c) {
       if (h->precision == SEIS_FP64) return launch_correct_plain<double>(N, h->d64, e0, ne, parity, h->stream);
       return launch_correct_plain<float>(N, h->d32, e0, ne, parity, h->stream);
     }
-    return tuned_correct(h->tuned, h->precision, N, e0, ne, parity, h->stream);
+    return tuned_correct(h->tuned, h->precision, N, e0, M.iface_start[c], e0 + ne, parity, h->stream);
   });
   if (st != hipSuccess) return hip_fail(h, st, "correct launch");
   return SEIS_OK;
@@ -391,20 +393,20 @@ int seis_write(seis_t* h, const double* dofs, const double* eta) {
   Model& M = h->M;
   HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
   if (dofs) {
-    const int64_t n = M.E * M.B * 9;
+    const int RT = row_tiles(M.B);
+    const int64_t n = q_size(M.E, RT);
     const size_t row = (size_t)M.B * 9;
+    std::vector<double> tmp(n, 0.0);
+    for (int64_t k = 0; k < M.E; ++k) {
+      const double* src = dofs + M.old_of_new[k] * row;
+      for (int r = 0; r < M.B; ++r)
+        for (int p = 0; p < 9; ++p) tmp[qidx(k, r, p, RT)] = src[r * 9 + p];
+    }
     if (h->precision == SEIS_FP64) {
-      std::vector<double> tmp(n);
-      for (int64_t k = 0; k < M.E; ++k)
-        std::memcpy(&tmp[k * row], dofs + M.old_of_new[k] * row, row * sizeof(double));
       HIPCHK(h, hipMemcpy(h->d64.Q, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice), "write Q");
     } else {
-      std::vector<float> tmp(n);
-      for (int64_t k = 0; k < M.E; ++k) {
-        const double* src = dofs + M.old_of_new[k] * row;
-        for (size_t i = 0; i < row; ++i) tmp[k * row + i] = (float)src[i];
-      }
-      HIPCHK(h, hipMemcpy(h->d32.Q, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice), "write Q");
+      std::vector<float> tf(tmp.begin(), tmp.end());
+      HIPCHK(h, hipMemcpy(h->d32.Q, tf.data(), n * sizeof(float), hipMemcpyHostToDevice), "write Q");
     }
   }
   if (eta && !M.g_elem.empty()) {
@@ -477,20 +479,21 @@ int seis_read(seis_t* h, double* dofs, double* eta) {
   Model& M = h->M;
   HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
   if (dofs) {
-    const int64_t n = M.E * M.B * 9;
+    const int RT = row_tiles(M.B);
+    const int64_t n = q_size(M.E, RT);
     const size_t row = (size_t)M.B * 9;
+    std::vector<double> tmp(n);
     if (h->precision == SEIS_FP64) {
-      std::vector<double> tmp(n);
       HIPCHK(h, hipMemcpy(tmp.data(), h->d64.Q, n * sizeof(double), hipMemcpyDeviceToHost), "read Q");
-      for (int64_t k = 0; k < M.E; ++k)
-        std::memcpy(dofs + M.old_of_new[k] * row, &tmp[k * row], row * sizeof(double));
     } else {
-      std::vector<float> tmp(n);
-      HIPCHK(h, hipMemcpy(tmp.data(), h->d32.Q, n * sizeof(float), hipMemcpyDeviceToHost), "read Q");
-      for (int64_t k = 0; k < M.E; ++k) {
-        double* dst = dofs + M.old_of_new[k] * row;
-        for (size_t i = 0; i < row; ++i) dst[i] = tmp[k * row + i];
-      }
+      std::vector<float> tf(n);
+      HIPCHK(h, hipMemcpy(tf.data(), h->d32.Q, n * sizeof(float), hipMemcpyDeviceToHost), "read Q");
+      for (int64_t i = 0; i < n; ++i) tmp[i] = tf[i];
+    }
+    for (int64_t k = 0; k < M.E; ++k) {
+      double* dst = dofs + M.old_of_new[k] * row;
+      for (int r = 0; r < M.B; ++r)
+        for (int p = 0; p < 9; ++p) dst[r * 9 + p] = tmp[qidx(k, r, p, RT)];
     }
   }
   if (eta && !M.g_elem.empty()) {
@@ -506,18 +509,22 @@ int seis_read_elements(seis_t* h, const int64_t* ids, int64_t n, double* dofs) {
   Model& M = h->M;
   HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
   const size_t row = (size_t)M.B * 9;
+  const int RT = row_tiles(M.B);
+  const int64_t gsz = (int64_t)RT * 36 * 64;  // values of one 16-element group
+  std::vector<double> blk(gsz);
+  std::vector<float> blkf(gsz);
   for (int64_t i = 0; i < n; ++i) {
     if (ids[i] < 0 || ids[i] >= M.E) return fail(h, SEIS_ERANGE, "element id out of range");
     const int64_t k = M.new_of_old[ids[i]];
+    const int64_t base = (k >> 4) * gsz;
     if (h->precision == SEIS_FP64) {
-      HIPCHK(h, hipMemcpy(dofs + i * row, h->d64.Q + k * row, row * sizeof(double), hipMemcpyDeviceToHost),
-             "read element");
+      HIPCHK(h, hipMemcpy(blk.data(), h->d64.Q + base, gsz * sizeof(double), hipMemcpyDeviceToHost), "read element");
     } else {
-      std::vector<float> tmp(row);
-      HIPCHK(h, hipMemcpy(tmp.data(), h->d32.Q + k * row, row * sizeof(float), hipMemcpyDeviceToHost),
-             "read element");
-      for (size_t j = 0; j < row; ++j) dofs[i * row + j] = tmp[j];
+      HIPCHK(h, hipMemcpy(blkf.data(), h->d32.Q + base, gsz * sizeof(float), hipMemcpyDeviceToHost), "read element");
+      for (int64_t j = 0; j < gsz; ++j) blk[j] = blkf[j];
     }
+    for (int r = 0; r < M.B; ++r)
+      for (int p = 0; p < 9; ++p) dofs[i * row + r * 9 + p] = blk[qidx(k, r, p, RT) - base];
   }
   return SEIS_OK;
 }

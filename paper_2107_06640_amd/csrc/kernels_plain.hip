@@ -13,6 +13,7 @@
 // Neighbour part (corrector): Q -= sum_i L_i (F~+_i In_i).
 #include "device.hpp"
 #include "elastic.hpp"
+#include "layout.hpp"
 
 namespace seis {
 
@@ -24,6 +25,7 @@ template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, int parity) {
   constexpr int B = nbasis(N), Bf = nface(N);
   constexpr int B1 = nbasis(N - 1);
+  constexpr int RT = row_tiles(B), FT = row_tiles(Bf);
   const int64_t e = e0 + blockIdx.x;
   const int tid = threadIdx.x;
   __shared__ T sD[B * 9], sI[B * 9], sIh[B * 9];
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, 
   const int gs = d.gslot[e];
   T* gD = gs >= 0 ? d.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
   for (int i = tid; i < B * 9; i += NT) {
-    const T q = d.Q[e * B * 9 + i];
+    const T q = d.Q[qidx(e, i / 9, i % 9, RT)];
     sD[i] = q;
     sI[i] = q;
     sIh[i] = q;
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, 
     const int32_t t = d.tgt[e * 4 + f];
     const int src = d.perm[d.hperm[e * 4 + f] * Bf + m];
     const T v = sV[(f * Bf + src) * 9 + p];
-    T* dst = d.In + ((int64_t)t * Bf + m) * 9 + p;
+    T* dst = d.In + inidx(t >> 2, t & 3, m, p, FT);
     if (md == 1) {
       *dst = v;
     } else if (md == 2) {
@@ -136,24 +138,28 @@ __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, 
       const T* L = d.Lf + ((size_t)f * B + kk) * Bf;
       for (int m = 0; m < Bf; ++m) acc -= L[m] * sVh[(f * Bf + m) * 9 + p];
     }
-    d.Q[e * B * 9 + i] += acc;
+    d.Q[qidx(e, kk, p, RT)] += acc;
   }
 }
 
 template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_correct_plain(DevData<T> d, int64_t e0, int parity) {
   constexpr int B = nbasis(N), Bf = nface(N);
+  constexpr int RT = row_tiles(B), FT = row_tiles(Bf);
   const int64_t e = e0 + blockIdx.x;
   const int tid = threadIdx.x;
   __shared__ T sW[4 * Bf * 9];
   for (int i = tid; i < 4 * Bf * 9; i += NT) {
     const int f = i / (Bf * 9), m = (i / 9) % Bf, p = i % 9;
     const int h2 = d.rhalf2[e * 4 + f];
-    const T* src = (parity && h2 >= 0) ? d.H2 + ((int64_t)h2 * Bf + m) * 9
-                                       : d.In + ((e * 4 + f) * Bf + m) * 9;
     const T* F = d.Fp + ((e * 4 + f) * 81 + p * 9);
     T a = T(0);
-    for (int r = 0; r < 9; ++r) a += F[r] * src[r];
+    if (parity && h2 >= 0) {
+      const T* src = d.H2 + ((int64_t)h2 * Bf + m) * 9;
+      for (int r = 0; r < 9; ++r) a += F[r] * src[r];
+    } else {
+      for (int r = 0; r < 9; ++r) a += F[r] * d.In[inidx(e, f, m, r, FT)];
+    }
     sW[i] = a;
   }
   __syncthreads();
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(NT) void k_correct_plain(DevData<T> d, int64_t e0, 
       const T* L = d.Lf + ((size_t)f * B + kk) * Bf;
       for (int m = 0; m < Bf; ++m) acc += L[m] * sW[(f * Bf + m) * 9 + p];
     }
-    d.Q[e * B * 9 + i] -= acc;
+    d.Q[qidx(e, kk, p, RT)] -= acc;
   }
 }
 
@@ -176,6 +182,7 @@ __global__ __launch_bounds__(NT) void k_correct_plain(DevData<T> d, int64_t e0, 
 template <typename T, int N>
 __global__ __launch_bounds__(64) void k_gravity(DevData<T> d, const int32_t* glist) {
   constexpr int B = nbasis(N);
+  constexpr int RT = row_tiles(B);
   constexpr int nq = (N + 1) * (N + 1);
   const int gf = glist[blockIdx.x];
   const int tid = threadIdx.x;
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(64) void k_gravity(DevData<T> d, const int32_t* gli
     } else {
       continue;
     }
-    d.Q[e * B * 9 + i] -= (T)(scale * acc);
+    d.Q[qidx(e, kk, p, RT)] -= (T)(scale * acc);
   }
 }
 

@@ -1,0 +1,40 @@
+// Device layouts of the element state and of the face inboxes.
+//
+// Elements are processed by 64-lane wavefronts in groups of 16. Inside a
+// group the data is stored in the order in which a wavefront holds it in the
+// output fragments of a 16x16 matrix-core product: for row tile t (rows
+// 16t..16t+15), value slot v (0..3) and quantity p, 64 consecutive values in
+// lane order, lane = el + 16 g holding element el of the group at row
+// 16t + 4g + v. One register of the wavefront is then one coalesced
+// 256-byte load or store, and the plain kernels reach any (element, row,
+// quantity) through the same index function.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace seis {
+
+__host__ __device__ constexpr int row_tiles(int rows) { return (rows + 15) / 16; }
+
+// Q[e][r][p] with RT row tiles per element.
+__host__ __device__ inline int64_t qidx(int64_t e, int r, int p, int RT) {
+  const int64_t grp = e >> 4;
+  const int el = int(e & 15);
+  const int t = r >> 4, g = (r >> 2) & 3, v = r & 3;
+  return (((grp * RT + t) * 4 + v) * 9 + p) * 64 + el + 16 * g;
+}
+
+// In[e][f][m][p] with FT node tiles per face.
+__host__ __device__ inline int64_t inidx(int64_t e, int f, int m, int p, int FT) {
+  const int64_t grp = e >> 4;
+  const int el = int(e & 15);
+  const int t = m >> 4, g = (m >> 2) & 3, v = m & 3;
+  return ((((grp * 4 + f) * FT + t) * 4 + v) * 9 + p) * 64 + el + 16 * g;
+}
+
+// Sizes (values) of the padded arrays for E elements.
+__host__ __device__ inline int64_t q_size(int64_t E, int RT) { return ((E + 15) >> 4) * RT * 4 * 9 * 64; }
+__host__ __device__ inline int64_t in_size(int64_t E, int FT) { return ((E + 15) >> 4) * 4 * FT * 4 * 9 * 64; }
+
+}  // namespace seis

@@ -27,6 +27,7 @@ struct Model {
   double dt_min = 0.0;
   std::vector<double> dt_c;            // [C]
   std::vector<int64_t> cluster_start;  // [C+1]
+  std::vector<int64_t> iface_start;    // [C]: first element of cluster c with a neighbour in another cluster
   std::vector<int64_t> new_of_old;     // [E]
   std::vector<int64_t> old_of_new;     // [E]
   std::vector<int32_t> cluster_old;    // [E], caller order
@@ -35,6 +36,10 @@ struct Model {
   std::vector<double> G;               // [E][9] dt_c * Jinv, row d, column e: d xi_d / d x_e
   std::vector<double> mat;             // [E][3] lambda, mu, 1/rho
   std::vector<double> Fm, Fp;          // [E][4][81] scaled flux matrices (row p, column r)
+  // pointwise form of the same flux: [E][4][12] = n_x, n_y, n_z, then the scaled
+  // middle-state coefficients (s_n, v_n from s_n, v_n; t_t, v_t from t_t, v_t) of
+  // the own trace (RCm, ghosts folded in) and of the neighbour trace (RCp)
+  std::vector<double> RCm, RCp;
   std::vector<int32_t> tgt;            // [E][4] writer: K*4 + i of the receiving face, -1 none
   std::vector<int8_t> mode;            // [E][4] writer FaceMode
   std::vector<int8_t> hperm;           // [E][4] writer node map index (0..5)

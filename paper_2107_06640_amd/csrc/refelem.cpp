@@ -312,6 +312,9 @@ RefElement build_reference(int N) {
       for (int m2 = 0; m2 < Bf; ++m2)
         if (nodes[m2][0] == bp[1] && nodes[m2][1] == bp[2]) R.perm[hh * Bf + m] = m2;
     }
+  R.pinv.assign(6 * Bf, -1);
+  for (int hh = 0; hh < 6; ++hh)
+    for (int m = 0; m < Bf; ++m) R.pinv[hh * Bf + R.perm[hh * Bf + m]] = m;
   return R;
 }
 

@@ -135,6 +135,46 @@ void middle_state(double zpm, double zsm, double zpp, double zsp, M9& Gm, M9& Gp
   }
 }
 
+// Middle-state coefficients of the pointwise Godunov solver (Sec. 4.2) in the
+// physical frame, scaled by s: with s_n = n.s.n, t_t = s n - s_n n,
+// v_n = v.n, v_t = v - v_n n of a trace,
+//   s_n^b = c0 s_n + c1 v_n,  v_n^b = c2 s_n + c3 v_n,
+//   t_t^b = c4 t_t + c5 v_t,  v_t^b = c6 t_t + c7 v_t
+// summed over the own trace (cm) and the neighbour trace (cp); the flux is
+// then A-hat^-(n) applied to (v^b, traction s_n^b n + t_t^b). Ghost states of
+// physical boundaries are folded into cm.
+void pointwise_coeffs(int kind, double zpm, double zsm, double zpp, double zsp, double s, double cm[8],
+                      double cp[8]) {
+  for (int i = 0; i < 8; ++i) cm[i] = cp[i] = 0.0;
+  if (kind == 2) return;  // gravity surface: handled by the eta ODE
+  const double c1 = zpm * zpp / (zpm + zpp);
+  double a[8], b[8];
+  a[0] = 1.0 - c1 / zpp; a[1] = -c1; b[0] = c1 / zpp; b[1] = c1;
+  a[2] = -c1 / (zpp * zpm); a[3] = 1.0 - c1 / zpm; b[2] = c1 / (zpp * zpm); b[3] = c1 / zpm;
+  if (zsm > 0.0 && zsp > 0.0) {
+    const double ct = zsm * zsp / (zsm + zsp);
+    a[4] = 1.0 - ct / zsp; a[5] = -ct; b[4] = ct / zsp; b[5] = ct;
+    a[6] = -ct / (zsp * zsm); a[7] = 1.0 - ct / zsm; b[6] = ct / (zsp * zsm); b[7] = ct / zsm;
+  } else if (zsm > 0.0) {
+    a[4] = a[5] = b[4] = b[5] = 0.0;
+    a[6] = -1.0 / zsm; a[7] = 1.0; b[6] = b[7] = 0.0;
+  } else {
+    for (int i = 4; i < 8; ++i) a[i] = b[i] = 0.0;
+  }
+  if (kind == 0 || kind == 1) {
+    for (int i = 0; i < 8; ++i) { cm[i] = s * a[i]; cp[i] = s * b[i]; }
+    return;
+  }
+  // ghost traces: absorbing 0; wall: same traction, velocity flipped; free: traction flipped
+  double gs = 0.0, gv = 0.0;
+  if (kind == 4) { gs = 1.0; gv = -1.0; }
+  if (kind == 5) { gs = -1.0; gv = 1.0; }
+  for (int i = 0; i < 8; i += 2) {
+    cm[i] = s * (a[i] + gs * b[i]);
+    cm[i + 1] = s * (a[i + 1] + gv * b[i + 1]);
+  }
+}
+
 struct FaceKey {
   int64_t k[3];
   int64_t id;  // element * 4 + face
@@ -395,22 +435,36 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
   for (int c = 0; c < C; ++c) M.dt_c[c] = std::ldexp(dmin, c);
   M.cluster_old = cl;
 
-  // ---- element order: by cluster, stable
+  // ---- element order: by cluster; inside a cluster, elements with a
+  // neighbour in another cluster last (stable)
+  std::vector<int8_t> iface(E, 0);
+  for (int64_t id = 0; id < E * 4; ++id)
+    if (nb[id] >= 0 && cl[nb[id] / 4] != cl[id / 4]) iface[id / 4] = 1;
   M.old_of_new.resize(E);
   std::iota(M.old_of_new.begin(), M.old_of_new.end(), 0);
-  std::stable_sort(M.old_of_new.begin(), M.old_of_new.end(),
-                   [&](int64_t a, int64_t b) { return cl[a] < cl[b]; });
+  std::stable_sort(M.old_of_new.begin(), M.old_of_new.end(), [&](int64_t a, int64_t b) {
+    if (cl[a] != cl[b]) return cl[a] < cl[b];
+    return iface[a] < iface[b];
+  });
   M.new_of_old.resize(E);
   for (int64_t k = 0; k < E; ++k) M.new_of_old[M.old_of_new[k]] = k;
   M.cluster_start.assign(C + 1, 0);
   for (int64_t e = 0; e < E; ++e) M.cluster_start[cl[e] + 1]++;
   for (int c = 0; c < C; ++c) M.cluster_start[c + 1] += M.cluster_start[c];
+  M.iface_start.assign(C, 0);
+  for (int c = 0; c < C; ++c) {
+    int64_t k = M.cluster_start[c];
+    while (k < M.cluster_start[c + 1] && !iface[M.old_of_new[k]]) ++k;
+    M.iface_start[c] = k;
+  }
 
   // ---- per element data (new order)
   M.G.assign(E * 9, 0.0);
   M.mat.assign(E * 3, 0.0);
   M.Fm.assign(E * 4 * 81, 0.0);
   M.Fp.assign(E * 4 * 81, 0.0);
+  M.RCm.assign(E * 4 * 12, 0.0);
+  M.RCp.assign(E * 4 * 12, 0.0);
   M.tgt.assign(E * 4, -1);
   M.mode.assign(E * 4, MODE_NONE);
   M.hperm.assign(E * 4, 0);
@@ -454,6 +508,21 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
       for (int i = 0; i < 81; ++i) {
         M.Fm[(k * 4 + f) * 81 + i] = scale * Fm[i];
         M.Fp[(k * 4 + f) * 81 + i] = scale * Fp[i];
+      }
+      double zpp = zpm, zsp = zsm;
+      if (kind == 0 || kind == 1) {
+        const int64_t e2 = nb[id] / 4;
+        zpp = std::sqrt((lam[e2] + 2 * mu[e2]) * rho[e2]);
+        zsp = std::sqrt(mu[e2] * rho[e2]);
+      }
+      double cm[8], cp[8];
+      pointwise_coeffs(kind, zpm, zsm, zpp, zsp, scale, cm, cp);
+      double* rm = &M.RCm[(k * 4 + f) * 12];
+      double* rp = &M.RCp[(k * 4 + f) * 12];
+      for (int d = 0; d < 3; ++d) rm[d] = rp[d] = normal[id * 3 + d];
+      for (int i = 0; i < 8; ++i) {
+        rm[3 + i] = cm[i];
+        rp[3 + i] = cp[i];
       }
     }
   }

@@ -1,4 +1,4 @@
-// Tuned (MFMA) element kernels: interface used by the C ABI.
+// Tuned (matrix-core) element kernels: interface used by the C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,20 +10,42 @@
 
 namespace seis {
 
+// Arguments of the tuned kernels (device pointers; FP32 state).
+struct TArgs {
+  float* Q;             // tiled [E][B][9]
+  float* In;            // tiled [E][4][Bf][9]
+  const float* G;       // [E][9]
+  const float* mat;     // [E][3]
+  const float* RCm;     // [E][4][12] own-trace flux coefficients
+  const float* RCp;     // [E][4][12] neighbour-trace flux coefficients
+  const int32_t* tgt;   // [E][4]
+  const int8_t* mode;   // [E][4]
+  const int8_t* hperm;  // [E][4]
+  const int32_t* pinv;  // [6][Bf]
+  const int32_t* gslot; // [E]
+  float* gD;            // [F_g][N+1][B][9]
+  const void* ref;      // reference matrices K | E | L in operand precision
+  int ref_bytes;
+};
+
 struct TunedData {
   int ready = 0;
   int N = 0;
   int precision = 0;
-  int tile = 0;
+  int waves = 4;   // wavefronts per work-group (16 elements each)
+  TArgs a{};
+  std::vector<int64_t> iface_start;   // per cluster: first element handled by the plain kernels
   DevData<double> d64{};
   DevData<float> d32{};
 };
 
 hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevData<double>& d64,
                        const DevData<float>& d32, int tile, std::vector<void*>& owned, int64_t& bytes);
-hipError_t tuned_predict(const TunedData& t, int precision, int N, int64_t e0, int64_t ne, int parity,
+// Elements [e0, ei) go to the matrix-core kernels, [ei, e1) (neighbours in
+// another LTS cluster) to the plain kernels.
+hipError_t tuned_predict(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
                          hipStream_t s);
-hipError_t tuned_correct(const TunedData& t, int precision, int N, int64_t e0, int64_t ne, int parity,
+hipError_t tuned_correct(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
                          hipStream_t s);
 
 }  // namespace seis

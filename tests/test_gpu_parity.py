@@ -161,3 +161,61 @@ def test_invalid_inputs_return_errors():
     bad.tet[0, 1] = bad.tet[0, 0]
     with pytest.raises(S.SeisError):
         S.from_mesh(bad, mats, 4)
+
+
+# ---------------------------------------------------------------------------
+# Tuned (matrix-core) kernels. FP32 operands: per-field relative L2 against the
+# FP64 oracle below 2e-5 over a few steps (FP32 round-off ~6e-8 per operation,
+# amplified by the CK chain and the Lagrange lift). BF16 operands: below 3e-2
+# (operand round-off 2^-9 per value; the state stays FP32).
+TOL32 = 2e-5
+TOL16 = 3e-2
+
+
+@pytest.mark.parametrize("order", [3, 4, 5, 6, 7])
+def test_tuned_fp32_coupled_gravity(order):
+    mesh, mats = inputs.coupled_box(4, 3, 4, cell=500.0, water_layers=2, jitter=0.15, seed=order)
+    o, d, e = run_pair(mesh, mats, order, 2, precision="fp32", kernel="tuned", seed=order)
+    fe = field_errors(d, o.Q, o.geo.absdet)
+    ee = np.abs(e - o.eta).max() / np.abs(o.eta).max()
+    say("tuned fp32 field errors", np.array2string(fe, precision=2), "eta", ee)
+    assert fe.max() < TOL32 and ee < TOL32
+
+
+def test_tuned_fp32_boundary_kinds_and_ragged_groups():
+    # 3*2*3*6 = 108 elements: 6 full 16-element groups and a ragged tail of 12
+    mesh = inputs.box_mesh(3, 2, 3, lengths=(3.0, 2.0, 3.0), jitter=0.2, seed=4,
+                           sides={"x-": "absorbing", "x+": "wall", "y-": "free", "y+": "free",
+                                  "z-": "absorbing", "z+": "wall"})
+    mats = inputs.uniform_materials(mesh, 2500.0, 5000.0, 2800.0)
+    o, d, e = run_pair(mesh, mats, 5, 3, precision="fp32", kernel="tuned")
+    fe = field_errors(d, o.Q, o.geo.absdet)
+    say("tuned fp32 boundary field errors", np.array2string(fe, precision=2))
+    assert fe.max() < TOL32
+
+
+def test_tuned_fp32_lts():
+    zn = np.array([0.0, 0.6, 0.85, 0.95, 1.0]) * 1000.0 - 1000.0
+    mesh, mats = inputs.coupled_box(4, 4, 4, cell=500.0, water_layers=1, z_nodes=zn)
+    o, d, e = run_pair(mesh, mats, 5, 2, precision="fp32", kernel="tuned", max_clusters=3)
+    assert o.n_clusters >= 2
+    fe = field_errors(d, o.Q, o.geo.absdet)
+    say("tuned fp32 lts field errors", np.array2string(fe, precision=2))
+    assert fe.max() < TOL32
+
+
+@pytest.mark.parametrize("order", [4, 6])
+def test_tuned_bf16_coupled_gravity(order):
+    mesh, mats = inputs.coupled_box(4, 3, 4, cell=500.0, water_layers=2, jitter=0.15, seed=order)
+    o, d, e = run_pair(mesh, mats, order, 2, precision="bf16", kernel="tuned", seed=order)
+    fe = field_errors(d, o.Q, o.geo.absdet)
+    ee = np.abs(e - o.eta).max() / np.abs(o.eta).max()
+    say("tuned bf16 field errors", np.array2string(fe, precision=2), "eta", ee)
+    assert fe.max() < TOL16 and ee < TOL16
+
+
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_tuned_tiles_agree(tile):
+    mesh, mats = inputs.coupled_box(4, 3, 4, cell=500.0, water_layers=2, jitter=0.15, seed=9)
+    o, d, e = run_pair(mesh, mats, 4, 1, precision="fp32", kernel="tuned", tile=tile, seed=9)
+    assert field_errors(d, o.Q, o.geo.absdet).max() < TOL32
