@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libseis.so")
+LIB_PATH = os.environ.get("SEIS_LIB", os.path.join(_HERE, "libseis.so"))
 
 SEIS_FP64, SEIS_FP32, SEIS_BF16 = 0, 1, 2
 SEIS_KERNEL_TUNED, SEIS_KERNEL_PLAIN = 0, 1
