@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--scale", type=int, default=1)
     ap.add_argument("--max-clusters", type=int, default=4)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each macro step as one hipGraph; kernel timings then come from a "
+                         "separate eagerly launched pass of the same length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many GiB (counter calibration)")
@@ -154,7 +157,8 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     s = seis.from_mesh(mesh, mats, args.order, precision=args.precision, kernel=args.kernel,
-                       max_clusters=args.max_clusters, stream=stream.cuda_stream, tile=args.tile)
+                       max_clusters=args.max_clusters, stream=stream.cuda_stream, tile=args.tile,
+                       graph=args.graph)
     inf = s.info()
     q = tiled_dofs(mesh.n_elements, inf["n_basis"], 0, mu == 0)
     s.write(q)
@@ -168,18 +172,26 @@ def main():
     s.sync()
     torch.cuda.synchronize()
 
-    s.profile(True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(args.steps):
-        s.step()
-    stop.record(stream)
-    stop.synchronize()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    prof = s.profile_read()
-    s.profile(False)
+    def timed_steps(profile):
+        s.profile(profile)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(args.steps):
+            s.step()
+        stop.record(stream)
+        stop.synchronize()
+        torch.cuda.synchronize()
+        prof = s.profile_read() if profile else None
+        s.profile(False)
+        return start.elapsed_time(stop), prof
+
+    if args.graph:
+        ms, _ = timed_steps(False)       # graph replays
+        eager_ms, prof = timed_steps(True)
+    else:
+        ms, prof = timed_steps(True)
+        eager_ms = ms
     upd = inf["updates_per_macro_step"] * args.steps
     value = upd / (ms / 1e3)
 
@@ -222,6 +234,7 @@ def main():
                                f"order {args.order} (B={inf['n_basis']}), rate-2 LTS {inf['n_clusters']} clusters "
                                f"{inf['cluster_size']}, {inf['n_gravity_faces']} gravity faces",
                    "kernel": args.kernel, "precision": args.precision, "elements": inf["n_elements"],
+                   "graph": bool(args.graph), "eager_ms_per_step": eager_ms / args.steps,
                    "updates_per_step": inf["updates_per_macro_step"]},
         "roofline": roof,
         "kernels_ms": {k: v[0] for k, v in prof.items()},

@@ -95,6 +95,8 @@ typedef struct {
   int max_clusters; /* rate-2 LTS clusters (Sec. 4.4); 1 = global time stepping */
   void *stream;     /* hipStream_t to launch on; NULL = the default stream */
   int tile;         /* elements per work-group for the tuned kernels; 0 = autotuned default */
+  int graph;        /* nonzero: seis_step captures its macro step into a hipGraph at its first
+                       call and replays that graph afterwards (one launch per macro step) */
 } seis_options_t;
 
 typedef struct {
@@ -114,7 +116,8 @@ typedef struct {
   int64_t device_bytes;
 } seis_info_t;
 
-/* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream. */
+/* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream,
+ * eager launches (no graph). */
 void seis_default_options(seis_options_t *opt);
 
 /* Build the solver for a mesh (Sec. 4.1-4.4): validate, match faces,
@@ -153,7 +156,11 @@ int seis_correct(seis_t *h, int c);
 /* One LTS macro step (2^(C-1) sub-steps of dt_min): in sub-step s the
  * predictors of the clusters with s mod 2^c == 0, then the correctors of the
  * clusters with (s+1) mod 2^c == 0 (Sec. 4.4). Launches asynchronously on the
- * handle's stream. */
+ * handle's stream. With options.graph set, the first call captures these
+ * launches into a hipGraph (on a private stream) and every later call
+ * launches that graph on the handle's stream. Kernel timings cannot be read
+ * from inside a graph: while profiling is on (seis_profile) the step is
+ * launched eagerly. */
 int seis_step(seis_t *h);
 
 /* Run n macro steps (same as calling seis_step n times). */

@@ -76,29 +76,27 @@ def adjacency(tet, face_kind, xyz, period):
     Returns nb [E, 4] (-1 on physical boundaries), nbf [E, 4], shift [E, 4, 3]
     such that a point x on the face corresponds to x + shift in the neighbour.
     """
-    tet = np.asarray(tet)
+    tet = np.asarray(tet, dtype=np.int64)
     face_kind = np.asarray(face_kind)
     E = tet.shape[0]
     nb = -np.ones((E, 4), dtype=np.int64)
     nbf = -np.ones((E, 4), dtype=np.int64)
     shift = np.zeros((E, 4, 3))
-    table = {}
-    for e in range(E):
-        for i in range(4):
-            if face_kind[e, i] != 0:
-                continue
-            key = tuple(sorted(int(tet[e, v]) for v in FACE_VERTS[i]))
-            if key in table:
-                e2, i2 = table.pop(key)
-                nb[e, i], nbf[e, i] = e2, i2
-                nb[e2, i2], nbf[e2, i2] = e, i
-            else:
-                table[key] = (e, i)
-    if table:
-        raise ValueError(f"{len(table)} interior faces have no neighbour")
+    # interior faces: sort the sorted vertex triples; a matched face is a run of two
+    ee, ff = np.nonzero(face_kind == 0)
+    if ee.size:
+        keys = np.sort(tet[ee[:, None], np.array(FACE_VERTS)[ff]], axis=1)
+        order = np.lexsort((keys[:, 2], keys[:, 1], keys[:, 0]))
+        k = keys[order]
+        pair = np.nonzero(np.all(k[1:] == k[:-1], axis=1))[0]
+        if 2 * pair.size != ee.size or np.any(np.diff(pair) < 2):
+            raise ValueError("interior faces without exactly one neighbour")
+        a, b = order[pair], order[pair + 1]
+        nb[ee[a], ff[a]], nbf[ee[a], ff[a]] = ee[b], ff[b]
+        nb[ee[b], ff[b]], nbf[ee[b], ff[b]] = ee[a], ff[a]
     # periodic faces: match centroids modulo the period
     period = np.asarray(period, dtype=np.float64)
-    per = [(e, i) for e in range(E) for i in range(4) if face_kind[e, i] == 1]
+    per = [(int(e), int(i)) for e, i in np.argwhere(face_kind == 1)]
     if per:
         L = max(float(np.max(np.abs(xyz))), 1.0)
         cen = {}

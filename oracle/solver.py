@@ -55,16 +55,14 @@ def assign_clusters(dt_elem, nb, max_clusters):
     dt_min = float(dt_elem.min())
     c = np.floor(np.log2(dt_elem / dt_min)).astype(np.int64)
     c = np.clip(c, 0, max_clusters - 1)
-    E = c.size
-    changed = True
-    while changed:
-        changed = False
-        for e in range(E):
-            for i in range(4):
-                j = nb[e, i]
-                if j >= 0 and c[e] > c[j] + 1:
-                    c[e] = c[j] + 1
-                    changed = True
+    # lower c_K to c_J + 1 wherever a face neighbour J is more than one cluster
+    # finer, until nothing changes (the largest assignment obeying the rule)
+    while True:
+        nbc = np.where(nb >= 0, c[np.maximum(nb, 0)], max_clusters)
+        low = np.minimum(c, nbc.min(axis=1) + 1)
+        if np.array_equal(low, c):
+            break
+        c = low
     return c, dt_min
 
 
@@ -78,7 +76,7 @@ class Oracle:
     """
 
     def __init__(self, xyz, tet, face_kind, period, rho, lam, mu, N, *, cfl=0.35,
-                 g=9.81, max_clusters=1, cluster_of=None):
+                 g=9.81, max_clusters=1, cluster_of=None, dt_min=None):
         self.N = N
         self.B = bas.n_basis(N)
         self.geo = Geometry(xyz, tet)
@@ -110,6 +108,9 @@ class Oracle:
         else:
             self.cluster = np.asarray(cluster_of, dtype=np.int64)
             self.dt_min = float(self.dt_elem.min())
+        if dt_min is not None:
+            # a patch cut out of a larger mesh steps with that mesh's dt_min
+            self.dt_min = float(dt_min)
         self.n_clusters = int(self.cluster.max()) + 1
         self.members = [np.nonzero(self.cluster == c)[0] for c in range(self.n_clusters)]
         self.pos = np.empty(E, dtype=np.int64)

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/seis.h"
+#include "assemble.hpp"
 #include "device.hpp"
 #include "layout.hpp"
 #include "model.hpp"
@@ -71,6 +72,11 @@ struct seis_t {
   std::vector<Rec> recs;
   double tot_ms[3] = {0, 0, 0};
   int64_t tot_launch[3] = {0, 0, 0}, tot_elem[3] = {0, 0, 0};
+  // hipGraph of one macro step (options.graph)
+  bool use_graph = false;
+  hipStream_t cap = nullptr;            // private capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -114,10 +120,11 @@ int build_dev(seis_t* h, DevData<T>& d) {
   const int RT = row_tiles(B), FT = row_tiles(Bf);
   HIPCHK(h, b.alloc(&Q, q_size(E, RT)), "alloc Q");
   HIPCHK(h, hipMemset(Q, 0, q_size(E, RT) * sizeof(T)), "memset Q");
-  HIPCHK(h, upload(b, &G, M.G), "upload G");
-  HIPCHK(h, upload(b, &mat, M.mat), "upload mat");
-  HIPCHK(h, upload(b, &Fm, M.Fm), "upload Fm");
-  HIPCHK(h, upload(b, &Fp, M.Fp), "upload Fp");
+  // operators: filled on the device by the assembly kernel
+  HIPCHK(h, b.alloc(&G, E * 9), "alloc G");
+  HIPCHK(h, b.alloc(&mat, E * 3), "alloc mat");
+  HIPCHK(h, b.alloc(&Fm, E * 4 * 81), "alloc Fm");
+  HIPCHK(h, b.alloc(&Fp, E * 4 * 81), "alloc Fp");
   HIPCHK(h, b.alloc(&In, in_size(E, FT)), "alloc In");
   HIPCHK(h, hipMemset(In, 0, in_size(E, FT) * sizeof(T)), "memset In");
   HIPCHK(h, b.alloc(&H2, std::max<int64_t>(M.n_half2, 1) * Bf * 9), "alloc H2");
@@ -179,6 +186,56 @@ int build_common(seis_t* h, DevData<double>& c) {
   return SEIS_OK;
 }
 
+// FP64 assembly of G, material, F-+ and the pointwise flux coefficients on the
+// device (assemble.hpp); the host inputs are released afterwards.
+int assemble_ops(seis_t* h) {
+  Model& M = h->M;
+  Buffers tmp;
+  double *Ji, *ad, *dt, *lmr, *nrm, *area;
+  int8_t* kind;
+  int64_t* nbk;
+  auto bail = [&](hipError_t st, const char* w) {
+    tmp.release();
+    return hip_fail(h, st, w);
+  };
+  hipError_t st = upload(tmp, &Ji, M.a_Jinv);
+  if (st == hipSuccess) st = upload(tmp, &ad, M.a_absdet);
+  if (st == hipSuccess) st = upload(tmp, &dt, M.a_dt);
+  if (st == hipSuccess) st = upload(tmp, &lmr, M.a_lmr);
+  if (st == hipSuccess) st = upload(tmp, &nrm, M.a_nrm);
+  if (st == hipSuccess) st = upload(tmp, &area, M.a_area);
+  if (st == hipSuccess) st = upload(tmp, &kind, M.a_kind);
+  if (st == hipSuccess) st = upload(tmp, &nbk, M.a_nbk);
+  if (st != hipSuccess) return bail(st, "upload assembly inputs");
+  const AsmInput in{M.E, Ji, ad, dt, lmr, nrm, area, kind, nbk};
+  const bool tuned = h->kernel == SEIS_KERNEL_TUNED && h->precision != SEIS_FP64;
+  float* rcm = tuned ? const_cast<float*>(h->tuned.a.RCm) : nullptr;
+  float* rcp = tuned ? const_cast<float*>(h->tuned.a.RCp) : nullptr;
+  if (h->precision == SEIS_FP64) {
+    DevData<double>& d = h->d64;
+    const AsmOutput<double> out{const_cast<double*>(d.G), const_cast<double*>(d.mat), const_cast<double*>(d.Fm),
+                                const_cast<double*>(d.Fp), nullptr, nullptr};
+    st = launch_assemble(in, out, nullptr);
+  } else {
+    DevData<float>& d = h->d32;
+    const AsmOutput<float> out{const_cast<float*>(d.G), const_cast<float*>(d.mat), const_cast<float*>(d.Fm),
+                               const_cast<float*>(d.Fp), rcm, rcp};
+    st = launch_assemble(in, out, nullptr);
+  }
+  if (st == hipSuccess) st = hipDeviceSynchronize();
+  if (st != hipSuccess) return bail(st, "operator assembly");
+  tmp.release();
+  std::vector<double>().swap(M.a_Jinv);
+  std::vector<double>().swap(M.a_absdet);
+  std::vector<double>().swap(M.a_dt);
+  std::vector<double>().swap(M.a_lmr);
+  std::vector<double>().swap(M.a_nrm);
+  std::vector<double>().swap(M.a_area);
+  std::vector<int8_t>().swap(M.a_kind);
+  std::vector<int64_t>().swap(M.a_nbk);
+  return SEIS_OK;
+}
+
 hipEvent_t next_event(seis_t* h) {
   if (h->used == h->pool.size()) {
     hipEvent_t ev;
@@ -189,11 +246,11 @@ hipEvent_t next_event(seis_t* h) {
 }
 
 // fold recorded event pairs into the totals
-hipError_t fold_profile(seis_t* h) {
-  if (h->recs.empty()) return hipSuccess;
-  hipError_t st = hipEventSynchronize(h->recs.back().b);
+hipError_t fold_list(seis_t* h, const std::vector<seis_t::Rec>& recs) {
+  if (recs.empty()) return hipSuccess;
+  hipError_t st = hipEventSynchronize(recs.back().b);
   if (st != hipSuccess) return st;
-  for (auto& r : h->recs) {
+  for (const auto& r : recs) {
     float ms = 0.0f;
     st = hipEventElapsedTime(&ms, r.a, r.b);
     if (st != hipSuccess) return st;
@@ -201,9 +258,14 @@ hipError_t fold_profile(seis_t* h) {
     h->tot_launch[r.kind] += 1;
     h->tot_elem[r.kind] += r.n;
   }
+  return hipSuccess;
+}
+
+hipError_t fold_profile(seis_t* h) {
+  hipError_t st = fold_list(h, h->recs);
   h->recs.clear();
   h->used = 0;
-  return hipSuccess;
+  return st;
 }
 
 // launch fn() bracketed by events when profiling
@@ -300,6 +362,9 @@ void maybe_advance(seis_t* h) {
   }
 }
 
+int step_eager(seis_t* h);
+int step_graph(seis_t* h);
+
 }  // namespace
 
 extern "C" {
@@ -313,6 +378,7 @@ void seis_default_options(seis_options_t* o) {
   o->max_clusters = 1;
   o->stream = nullptr;
   o->tile = 0;
+  o->graph = 0;
 }
 
 int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, const seis_options_t* opt,
@@ -360,6 +426,7 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
   h->kernel = o.kernel;
   h->tile = o.tile;
   h->stream = (hipStream_t)o.stream;
+  h->use_graph = o.graph != 0;
   int rc = build_common(h, h->d64);
   if (rc == SEIS_OK) {
     if (o.precision == SEIS_FP64) {
@@ -373,6 +440,7 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
     hipError_t st = tuned_build(h->tuned, h->M, h->precision, h->d64, h->d32, h->tile, h->buf.ptrs, h->buf.bytes);
     if (st != hipSuccess) rc = hip_fail(h, st, "tuned set-up");
   }
+  if (rc == SEIS_OK) rc = assemble_ops(h);
   if (rc == SEIS_OK) {
     hipError_t st = hipDeviceSynchronize();
     if (st != hipSuccess) rc = hip_fail(h, st, "set-up sync");
@@ -449,6 +517,23 @@ int seis_correct(seis_t* h, int c) {
 int seis_step(seis_t* h) {
   if (!h) return SEIS_EINVAL;
   if (mid_step(h)) return fail(h, SEIS_EORDER, "a macro step is in progress; finish it with seis_predict/seis_correct");
+  if (h->use_graph) return step_graph(h);
+  return step_eager(h);
+}
+
+int seis_run(seis_t* h, int n) {
+  for (int i = 0; i < n; ++i) {
+    int rc = seis_step(h);
+    if (rc) return rc;
+  }
+  return SEIS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int step_eager(seis_t* h) {
   const int C = h->M.C;
   for (int s = 0; s < (1 << (C - 1)); ++s) {
     for (int c = 0; c < C; ++c)
@@ -465,13 +550,63 @@ int seis_step(seis_t* h) {
   return SEIS_OK;
 }
 
-int seis_run(seis_t* h, int n) {
-  for (int i = 0; i < n; ++i) {
-    int rc = seis_step(h);
-    if (rc) return rc;
+void drop_graph(seis_t* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+}
+
+// Capture the launches of one macro step on the private stream. The schedule
+// cursor is restored afterwards: capturing runs nothing.
+int capture_step(seis_t* h) {
+  drop_graph(h);
+  if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking), "capture stream");
+  const int sub = h->sub;
+  const int64_t done = h->macro_done;
+  const std::vector<int> pred = h->predicted, corr = h->corrected;
+  hipStream_t user = h->stream;
+  h->stream = h->cap;
+  hipError_t st = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+  int rc = SEIS_OK;
+  if (st == hipSuccess) rc = step_eager(h);
+  hipGraph_t g = nullptr;
+  const hipError_t se = st == hipSuccess ? hipStreamEndCapture(h->cap, &g) : st;
+  h->stream = user;
+  h->sub = sub;
+  h->macro_done = done;
+  h->predicted = pred;
+  h->corrected = corr;
+  if (rc != SEIS_OK || se != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != SEIS_OK) return rc;
+    return hip_fail(h, se, "graph capture");
+  }
+  h->graph = g;
+  st = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  if (st != hipSuccess) {
+    drop_graph(h);
+    return hip_fail(h, st, "graph instantiate");
   }
   return SEIS_OK;
 }
+
+// Graph replay of a macro step. Kernel timings cannot be read from inside a
+// graph, so with profiling on the step is launched eagerly instead.
+int step_graph(seis_t* h) {
+  if (h->prof) return step_eager(h);
+  if (!h->gexec) {
+    int rc = capture_step(h);
+    if (rc != SEIS_OK) return rc;
+  }
+  HIPCHK(h, hipGraphLaunch(h->gexec, h->stream), "graph launch");
+  h->macro_done++;
+  return SEIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int seis_read(seis_t* h, double* dofs, double* eta) {
   if (!h) return SEIS_EINVAL;
@@ -594,6 +729,8 @@ int seis_sync(seis_t* h) {
 void seis_destroy(seis_t* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  drop_graph(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   for (hipEvent_t ev : h->pool) (void)hipEventDestroy(ev);
   h->buf.release();
   delete h;

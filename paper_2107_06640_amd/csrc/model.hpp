@@ -32,14 +32,15 @@ struct Model {
   std::vector<int64_t> old_of_new;     // [E]
   std::vector<int32_t> cluster_old;    // [E], caller order
 
-  // per element (library order)
-  std::vector<double> G;               // [E][9] dt_c * Jinv, row d, column e: d xi_d / d x_e
-  std::vector<double> mat;             // [E][3] lambda, mu, 1/rho
-  std::vector<double> Fm, Fp;          // [E][4][81] scaled flux matrices (row p, column r)
-  // pointwise form of the same flux: [E][4][12] = n_x, n_y, n_z, then the scaled
-  // middle-state coefficients (s_n, v_n from s_n, v_n; t_t, v_t from t_t, v_t) of
-  // the own trace (RCm, ghosts folded in) and of the neighbour trace (RCp)
-  std::vector<double> RCm, RCp;
+  // per element inputs of the operator assembly (library order, FP64; see assemble.hpp)
+  std::vector<double> a_Jinv;          // [E][9]
+  std::vector<double> a_absdet;        // [E]
+  std::vector<double> a_dt;            // [E]
+  std::vector<double> a_lmr;           // [E][3] lambda, mu, rho
+  std::vector<double> a_nrm;           // [E][4][3]
+  std::vector<double> a_area;          // [E][4]
+  std::vector<int8_t> a_kind;          // [E][4]
+  std::vector<int64_t> a_nbk;          // [E][4] neighbour (library order), -1 none
   std::vector<int32_t> tgt;            // [E][4] writer: K*4 + i of the receiving face, -1 none
   std::vector<int8_t> mode;            // [E][4] writer FaceMode
   std::vector<int8_t> hperm;           // [E][4] writer node map index (0..5)

@@ -1,5 +1,6 @@
 // Mesh set-up of the library (host, FP64): validation, geometry, face
-// matching, Godunov flux matrices, LTS clusters and element order.
+// matching, LTS clusters, element order and the inputs of the operator
+// assembly, which runs on the GPU.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -14,166 +15,6 @@ namespace seis {
 namespace {
 
 const int FACE_V[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
-
-using M9 = std::array<double, 81>;
-
-M9 zero9() {
-  M9 m;
-  m.fill(0.0);
-  return m;
-}
-M9 mul9(const M9& a, const M9& b) {
-  M9 c = zero9();
-  for (int i = 0; i < 9; ++i)
-    for (int k = 0; k < 9; ++k) {
-      const double v = a[i * 9 + k];
-      if (v == 0.0) continue;
-      for (int j = 0; j < 9; ++j) c[i * 9 + j] += v * b[k * 9 + j];
-    }
-  return c;
-}
-
-// x-direction Jacobian of the velocity-stress system (Sec. 3 PDE written as
-// q_t + A q_x + ... = 0): stress rows pick up -(lambda delta_ij + mu ...) dv/dx,
-// velocity rows -(1/rho) d s_xj / dx.
-M9 jacobian_x(double lam, double mu, double rho) {
-  M9 A = zero9();
-  A[0 * 9 + 6] = -(lam + 2 * mu);
-  A[1 * 9 + 6] = -lam;
-  A[2 * 9 + 6] = -lam;
-  A[3 * 9 + 7] = -mu;
-  A[5 * 9 + 8] = -mu;
-  A[6 * 9 + 0] = -1.0 / rho;
-  A[7 * 9 + 3] = -1.0 / rho;
-  A[8 * 9 + 5] = -1.0 / rho;
-  return A;
-}
-
-// T(n) of the rotational invariance A-hat = T A T^-1 (Sec. 4.2): block-diagonal
-// with the stress transformation (R s R^T in Voigt form) and R = [n s t].
-void rotation(const double n[3], M9& T, M9& Tinv) {
-  double e[3] = {0, 0, 0};
-  int k = 0;
-  for (int d = 1; d < 3; ++d)
-    if (std::fabs(n[d]) < std::fabs(n[k])) k = d;
-  e[k] = 1.0;
-  const double en = e[0] * n[0] + e[1] * n[1] + e[2] * n[2];
-  double s[3] = {e[0] - en * n[0], e[1] - en * n[1], e[2] - en * n[2]};
-  const double ns = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-  for (int d = 0; d < 3; ++d) s[d] /= ns;
-  const double t[3] = {n[1] * s[2] - n[2] * s[1], n[2] * s[0] - n[0] * s[2], n[0] * s[1] - n[1] * s[0]};
-  double R[3][3];
-  for (int d = 0; d < 3; ++d) {
-    R[d][0] = n[d];
-    R[d][1] = s[d];
-    R[d][2] = t[d];
-  }
-  const int vi[6] = {0, 1, 2, 0, 1, 0}, vj[6] = {0, 1, 2, 1, 2, 2};
-  T = zero9();
-  Tinv = zero9();
-  for (int a = 0; a < 6; ++a) {
-    double Ea[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    Ea[vi[a]][vj[a]] = 1.0;
-    Ea[vj[a]][vi[a]] = 1.0;
-    double G[3][3], L[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        double g = 0.0, l = 0.0;
-        for (int p = 0; p < 3; ++p)
-          for (int q = 0; q < 3; ++q) {
-            g += R[i][p] * Ea[p][q] * R[j][q];  // R E R^T
-            l += R[p][i] * Ea[p][q] * R[q][j];  // R^T E R
-          }
-        G[i][j] = g;
-        L[i][j] = l;
-      }
-    for (int b = 0; b < 6; ++b) {
-      T[b * 9 + a] = G[vi[b]][vj[b]];
-      Tinv[b * 9 + a] = L[vi[b]][vj[b]];
-    }
-  }
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      T[(6 + i) * 9 + 6 + j] = R[i][j];
-      Tinv[(6 + i) * 9 + 6 + j] = R[j][i];
-    }
-}
-
-// Middle state of the rotated Riemann problem, w^b = Gm w- + Gp w+
-// (Sec. 4.2, eigen-decomposition and boundary state). Rows of components the
-// flux does not read stay zero.
-void middle_state(double zpm, double zsm, double zpp, double zsp, M9& Gm, M9& Gp) {
-  Gm = zero9();
-  Gp = zero9();
-  const double c = zpm * zpp / (zpm + zpp);
-  Gm[0 * 9 + 0] = 1.0 - c / zpp;
-  Gm[0 * 9 + 6] = -c;
-  Gp[0 * 9 + 0] = c / zpp;
-  Gp[0 * 9 + 6] = c;
-  Gm[6 * 9 + 6] = 1.0 - c / zpm;
-  Gm[6 * 9 + 0] = -c / (zpp * zpm);
-  Gp[6 * 9 + 0] = c / (zpp * zpm);
-  Gp[6 * 9 + 6] = c / zpm;
-  const int pa[2] = {3, 5}, pb[2] = {7, 8};
-  for (int k = 0; k < 2; ++k) {
-    const int a = pa[k], b = pb[k];
-    if (zsm > 0.0 && zsp > 0.0) {
-      const double cs = zsm * zsp / (zsm + zsp);
-      Gm[a * 9 + a] = 1.0 - cs / zsp;
-      Gm[a * 9 + b] = -cs;
-      Gp[a * 9 + a] = cs / zsp;
-      Gp[a * 9 + b] = cs;
-      Gm[b * 9 + b] = 1.0 - cs / zsm;
-      Gm[b * 9 + a] = -cs / (zsp * zsm);
-      Gp[b * 9 + a] = cs / (zsp * zsm);
-      Gp[b * 9 + b] = cs / zsm;
-    } else if (zsm > 0.0) {  // elastic '-', acoustic '+': zero shear traction
-      Gm[b * 9 + b] = 1.0;
-      Gm[b * 9 + a] = -1.0 / zsm;
-    }
-    // acoustic '-': tangential state is multiplied by mu- = 0 in the flux
-  }
-}
-
-// Middle-state coefficients of the pointwise Godunov solver (Sec. 4.2) in the
-// physical frame, scaled by s: with s_n = n.s.n, t_t = s n - s_n n,
-// v_n = v.n, v_t = v - v_n n of a trace,
-//   s_n^b = c0 s_n + c1 v_n,  v_n^b = c2 s_n + c3 v_n,
-//   t_t^b = c4 t_t + c5 v_t,  v_t^b = c6 t_t + c7 v_t
-// summed over the own trace (cm) and the neighbour trace (cp); the flux is
-// then A-hat^-(n) applied to (v^b, traction s_n^b n + t_t^b). Ghost states of
-// physical boundaries are folded into cm.
-void pointwise_coeffs(int kind, double zpm, double zsm, double zpp, double zsp, double s, double cm[8],
-                      double cp[8]) {
-  for (int i = 0; i < 8; ++i) cm[i] = cp[i] = 0.0;
-  if (kind == 2) return;  // gravity surface: handled by the eta ODE
-  const double c1 = zpm * zpp / (zpm + zpp);
-  double a[8], b[8];
-  a[0] = 1.0 - c1 / zpp; a[1] = -c1; b[0] = c1 / zpp; b[1] = c1;
-  a[2] = -c1 / (zpp * zpm); a[3] = 1.0 - c1 / zpm; b[2] = c1 / (zpp * zpm); b[3] = c1 / zpm;
-  if (zsm > 0.0 && zsp > 0.0) {
-    const double ct = zsm * zsp / (zsm + zsp);
-    a[4] = 1.0 - ct / zsp; a[5] = -ct; b[4] = ct / zsp; b[5] = ct;
-    a[6] = -ct / (zsp * zsm); a[7] = 1.0 - ct / zsm; b[6] = ct / (zsp * zsm); b[7] = ct / zsm;
-  } else if (zsm > 0.0) {
-    a[4] = a[5] = b[4] = b[5] = 0.0;
-    a[6] = -1.0 / zsm; a[7] = 1.0; b[6] = b[7] = 0.0;
-  } else {
-    for (int i = 4; i < 8; ++i) a[i] = b[i] = 0.0;
-  }
-  if (kind == 0 || kind == 1) {
-    for (int i = 0; i < 8; ++i) { cm[i] = s * a[i]; cp[i] = s * b[i]; }
-    return;
-  }
-  // ghost traces: absorbing 0; wall: same traction, velocity flipped; free: traction flipped
-  double gs = 0.0, gv = 0.0;
-  if (kind == 4) { gs = 1.0; gv = -1.0; }
-  if (kind == 5) { gs = -1.0; gv = 1.0; }
-  for (int i = 0; i < 8; i += 2) {
-    cm[i] = s * (a[i] + gs * b[i]);
-    cm[i + 1] = s * (a[i + 1] + gv * b[i + 1]);
-  }
-}
 
 struct FaceKey {
   int64_t k[3];
@@ -458,13 +299,15 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
     M.iface_start[c] = k;
   }
 
-  // ---- per element data (new order)
-  M.G.assign(E * 9, 0.0);
-  M.mat.assign(E * 3, 0.0);
-  M.Fm.assign(E * 4 * 81, 0.0);
-  M.Fp.assign(E * 4 * 81, 0.0);
-  M.RCm.assign(E * 4 * 12, 0.0);
-  M.RCp.assign(E * 4 * 12, 0.0);
+  // ---- per element inputs of the operator assembly (new order)
+  M.a_Jinv.resize(E * 9);
+  M.a_absdet.resize(E);
+  M.a_dt.resize(E);
+  M.a_lmr.resize(E * 3);
+  M.a_nrm.resize(E * 12);
+  M.a_area.resize(E * 4);
+  M.a_kind.resize(E * 4);
+  M.a_nbk.assign(E * 4, -1);
   M.tgt.assign(E * 4, -1);
   M.mode.assign(E * 4, MODE_NONE);
   M.hperm.assign(E * 4, 0);
@@ -474,56 +317,18 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
   int64_t nh2 = 0;
   for (int64_t k = 0; k < E; ++k) {
     const int64_t e = M.old_of_new[k];
-    const double dt = M.dt_c[cl[e]];
-    for (int i = 0; i < 9; ++i) M.G[k * 9 + i] = dt * Jinv[e * 9 + i];
-    M.mat[k * 3 + 0] = lam[e];
-    M.mat[k * 3 + 1] = mu[e];
-    M.mat[k * 3 + 2] = 1.0 / rho[e];
-    const double zpm = std::sqrt((lam[e] + 2 * mu[e]) * rho[e]), zsm = std::sqrt(mu[e] * rho[e]);
-    const M9 A = jacobian_x(lam[e], mu[e], rho[e]);
+    for (int i = 0; i < 9; ++i) M.a_Jinv[k * 9 + i] = Jinv[e * 9 + i];
+    M.a_absdet[k] = absdet[e];
+    M.a_dt[k] = M.dt_c[cl[e]];
+    M.a_lmr[k * 3 + 0] = lam[e];
+    M.a_lmr[k * 3 + 1] = mu[e];
+    M.a_lmr[k * 3 + 2] = rho[e];
     for (int f = 0; f < 4; ++f) {
       const int64_t id = e * 4 + f;
-      const int kind = face_kind[id];
-      const double scale = 2.0 * area[id] * dt / absdet[e];
-      M9 T, Ti, Gm, Gp, Fm = zero9(), Fp = zero9();
-      rotation(&normal[id * 3], T, Ti);
-      if (kind == 0 || kind == 1) {
-        const int64_t e2 = nb[id] / 4;
-        const double zpp = std::sqrt((lam[e2] + 2 * mu[e2]) * rho[e2]), zsp = std::sqrt(mu[e2] * rho[e2]);
-        middle_state(zpm, zsm, zpp, zsp, Gm, Gp);
-        Fm = mul9(mul9(T, mul9(A, Gm)), Ti);
-        Fp = mul9(mul9(T, mul9(A, Gp)), Ti);
-      } else if (kind == 3 || kind == 4 || kind == 5) {
-        middle_state(zpm, zsm, zpm, zsm, Gm, Gp);
-        if (kind == 4 || kind == 5) {
-          // ghost w+ = diag(m) w-, with m flipping velocity (wall) or stress (free surface)
-          for (int r = 0; r < 9; ++r)
-            for (int c = 0; c < 9; ++c) {
-              const double m = (kind == 4) ? (c >= 6 ? -1.0 : 1.0) : (c < 6 ? -1.0 : 1.0);
-              Gm[r * 9 + c] += Gp[r * 9 + c] * m;
-            }
-        }
-        Fm = mul9(mul9(T, mul9(A, Gm)), Ti);
-      }
-      for (int i = 0; i < 81; ++i) {
-        M.Fm[(k * 4 + f) * 81 + i] = scale * Fm[i];
-        M.Fp[(k * 4 + f) * 81 + i] = scale * Fp[i];
-      }
-      double zpp = zpm, zsp = zsm;
-      if (kind == 0 || kind == 1) {
-        const int64_t e2 = nb[id] / 4;
-        zpp = std::sqrt((lam[e2] + 2 * mu[e2]) * rho[e2]);
-        zsp = std::sqrt(mu[e2] * rho[e2]);
-      }
-      double cm[8], cp[8];
-      pointwise_coeffs(kind, zpm, zsm, zpp, zsp, scale, cm, cp);
-      double* rm = &M.RCm[(k * 4 + f) * 12];
-      double* rp = &M.RCp[(k * 4 + f) * 12];
-      for (int d = 0; d < 3; ++d) rm[d] = rp[d] = normal[id * 3 + d];
-      for (int i = 0; i < 8; ++i) {
-        rm[3 + i] = cm[i];
-        rp[3 + i] = cp[i];
-      }
+      for (int d = 0; d < 3; ++d) M.a_nrm[k * 12 + f * 3 + d] = normal[id * 3 + d];
+      M.a_area[k * 4 + f] = area[id];
+      M.a_kind[k * 4 + f] = face_kind[id];
+      if (nb[id] >= 0) M.a_nbk[k * 4 + f] = M.new_of_old[nb[id] / 4];
     }
   }
   // writer-side hand-over of each face: element J (new kn) face j writes into neighbour K's face i

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 
@@ -41,12 +42,6 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 struct OpF32 {};
 struct OpBF16 {};
 
-template <int N>
-struct Dim {
-  static constexpr int B = nbasis(N), Bf = nface(N), B1 = nbasis(N - 1);
-  static constexpr int RT = row_tiles(B), FT = row_tiles(Bf), RT1 = row_tiles(B1);
-  static constexpr int nK = 3 * B * B1, nE = 4 * Bf * B, nL = 4 * B * Bf;
-};
 
 __host__ __device__ inline unsigned short f2bf(float x) {
   // round to nearest even
@@ -112,105 +107,124 @@ __device__ __forceinline__ void node_flux(const float* c, float lam, float mu, f
   out[8] = -rinv * (snb * nz + tbz);
 }
 
+// ---------------------------------------------------------------------------
+// Reference block in LDS. Natural row-major layouts (FP32) or rows padded to a
+// multiple of 4 entries (BF16, so that four consecutive K entries are one
+// aligned 8-byte read), followed by a zero tail. Fragment reads use
+// compile-time strides, so every read is a per-lane base plus an immediate
+// offset. Reads may run past a matrix into the next one or into the tail:
+// such entries are finite and only meet zero B values (K index beyond the
+// input rows) or feed output rows that are discarded.
 template <class Op>
 using RefT = typename std::conditional<std::is_same<Op, OpF32>::value, float, unsigned short>::type;
 
-// A(i, k) of a stored reference block: row-major R[i][k] (TR = false) or
-// R[k][i] (TR = true), ld columns, ni x nk entries. Indices are clamped into
-// the block: clamped entries only meet zero B values or feed output rows that
-// are discarded.
-template <bool TR, class RT_>
-__device__ __forceinline__ RT_ aref(const RT_* R, int ld, int ni, int nk, int i, int k) {
-  i = min(i, ni - 1);
-  k = min(k, nk - 1);
-  return TR ? R[k * ld + i] : R[i * ld + k];
+template <class Op, int N>
+struct Lay {
+  static constexpr bool BF = std::is_same<Op, OpBF16>::value;
+  static constexpr int B = nbasis(N), Bf = nface(N), B1 = nbasis(N - 1);
+  static constexpr int RT = row_tiles(B), FT = row_tiles(Bf), RT1 = row_tiles(B1);
+  static constexpr int r4(int x) { return BF ? (x + 3) / 4 * 4 : x; }
+  static constexpr int ldK = r4(B1);   // K^d[l < B][m < B1]   (volume: A(k,l) = K[k][l]; FP32 CK: A(m,l) = K[l][m])
+  static constexpr int ldT = r4(B);    // BF16 CK: (K^d)^T[m < B1][l < B]
+  static constexpr int ldE = r4(B);    // E_f[node < Bf][row < B]
+  static constexpr int ldL = r4(Bf);   // L_f[row < B][node < Bf]
+  static constexpr int nK = 3 * B * ldK;
+  static constexpr int nT = BF ? 3 * B1 * ldT : 0;
+  static constexpr int nE = 4 * Bf * ldE;
+  static constexpr int nL = 4 * B * ldL;
+  static constexpr int maxld = (ldK > ldE ? ldK : ldE) > ldL ? (ldK > ldE ? ldK : ldE) : ldL;
+  static constexpr int tail = 16 * (maxld > ldT ? maxld : ldT) + 64;
+  static constexpr int oK = 0, oT = nK, oE = nK + nT, oL = oE + nE;
+  static constexpr int total = oL + nL + tail;
+  static constexpr int bytes = (total * (BF ? 2 : 4) + 15) / 16 * 16;
+};
+
+// A zero the compiler cannot see through. Views built with it are re-read
+// from LDS where they are used, instead of being hoisted into registers for
+// the whole kernel (the reference block is loop-invariant).
+#ifndef SEIS_LAUNDER
+#define SEIS_LAUNDER 1
+#endif
+__device__ __forceinline__ int opaque_zero() {
+  int z = 0;
+#if SEIS_LAUNDER == 1
+  asm volatile("" : "+s"(z));
+#elif SEIS_LAUNDER == 2
+  asm("" : "+s"(z));
+#endif
+  return z;
 }
 
-// acc[mt][p] += sum_k A(16 mt + el, k) X[k][p] over the input rows k < nrows,
-// X held per lane as x[t][v][p] (row 16t + 4g + v).
-template <class Op, bool TR, int NT, int MT, int P>
-__device__ __forceinline__ void contract(f4 (&acc)[MT][P], const RefT<Op>* R, int ld, int ni, int nk,
-                                         const float (&x)[NT][4][P], int nrows, int el, int g) {
-  if constexpr (std::is_same<Op, OpF32>::value) {
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (16 * t + v >= nrows) continue;
-        const int k = 16 * t + 4 * g + v;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const float a = aref<TR>(R, ld, ni, nk, 16 * mt + el, k);
-#pragma unroll
-          for (int p = 0; p < P; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, x[t][v][p], acc[mt][p], 0, 0, 0);
-        }
-      }
-  } else {
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (16 * t >= nrows) continue;
-      const int k0 = 16 * t + 4 * g;
-      s4 b[P];
-#pragma unroll
-      for (int p = 0; p < P; ++p) b[p] = pack4(x[t][0][p], x[t][1][p], x[t][2][p], x[t][3][p]);
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        s4 a;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a[j] = (short)aref<TR>(R, ld, ni, nk, 16 * mt + el, k0 + j);
-#pragma unroll
-        for (int p = 0; p < P; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], acc[mt][p], 0, 0, 0);
-      }
-    }
+// One 16-element group block of a fragment-layout array (Q, J or a face
+// inbox) as a raw buffer: register r of the wavefront is the 256-byte slab at
+// byte offset 256 r, each lane reading its own dword. The per-register offset
+// goes to the scalar offset, so no per-access vector address is needed.
+struct GroupBuf {
+  __amdgpu_buffer_rsrc_t r;
+  int lane4;
+  int o;
+  __device__ __forceinline__ GroupBuf(const float* base, int bytes, int lane)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, bytes, 0x00020000)),
+        lane4(lane * 4), o(opaque_zero()) {}
+  __device__ __forceinline__ float ld(int reg) const {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, lane4, o + reg * 256, 0));
   }
-}
+  __device__ __forceinline__ void st(int reg, float x) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, lane4, o + reg * 256, 0);
+  }
+};
 
-// dq[mt][p] += sum_l A(16 mt + el, l) (dt A*_d I~[l])_p over l < nrows: the
-// star product of each input row is formed on the fly (lane-local) right
-// before it enters the matrix core, so it is never stored for all rows.
-template <class Op, int NT, int MT>
-__device__ __forceinline__ void contract_star(f4 (&acc)[MT][9], const RefT<Op>* R, int ld, int ni, int nk,
-                                              const float (&x)[NT][4][9], int nrows, const float* Gd, float lam,
-                                              float mu, float rinv, int el, int g) {
+// A(i, k) = R[i * LD + k] (row-major) or R[k * LD + i] (transposed store)
+template <class R, int LD, bool TR>
+struct View {
+  const R* p;
+  int o;
+  __device__ __forceinline__ View(const R* base) : p(base), o(opaque_zero()) {}
+  __device__ __forceinline__ R at(int i, int k) const { return TR ? p[o + k * LD + i] : p[o + i * LD + k]; }
+  // four consecutive K entries k0..k0+3 (BF16, row-major only)
+  __device__ __forceinline__ s4 at4(int i, int k0) const {
+    static_assert(!TR, "four-entry reads need the row-major store");
+    return *reinterpret_cast<const s4*>(p + o + i * LD + k0);
+  }
+};
+
+template <class Op, class V>
+__device__ __forceinline__ void mma_slice(f4& acc, const V& A, int i, int k, float b);
+
+// acc[mt][p] += sum_k A(16 mt + el, k) X[k][p]; X rows produced by rowfn(t, v, b[9])
+// for the input rows k < nrows (rows 16t + 4g + v of this lane).
+template <class Op, class V, int NT, int MT, class RowFn>
+__device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nrows, int el, int g, RowFn rowfn) {
   if constexpr (std::is_same<Op, OpF32>::value) {
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (16 * t + v >= nrows) continue;
+        float b[9];
+        rowfn(t, v, b);
         const int k = 16 * t + 4 * g + v;
-        float z[9];
-        apply_star(Gd[0], Gd[1], Gd[2], lam, mu, rinv, x[t][v], z);
-        const bool ok = k < nrows;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-          const float a = aref<false>(R, ld, ni, nk, 16 * mt + el, k);
+          const float a = A.at(16 * mt + el, k);
 #pragma unroll
-          for (int p = 0; p < 9; ++p)
-            acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ok ? z[p] : 0.0f, acc[mt][p], 0, 0, 0);
+          for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[p], acc[mt][p], 0, 0, 0);
         }
       }
   } else {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (16 * t >= nrows) continue;
-      const int k0 = 16 * t + 4 * g;
-      float z[4][9];
+      float bv[4][9];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        apply_star(Gd[0], Gd[1], Gd[2], lam, mu, rinv, x[t][v], z[v]);
-        if (k0 + v >= nrows)
-#pragma unroll
-          for (int p = 0; p < 9; ++p) z[v][p] = 0.0f;
-      }
+      for (int v = 0; v < 4; ++v) rowfn(t, v, bv[v]);
       s4 b[9];
 #pragma unroll
-      for (int p = 0; p < 9; ++p) b[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
+      for (int p = 0; p < 9; ++p) b[p] = pack4(bv[0][p], bv[1][p], bv[2][p], bv[3][p]);
+      const int k0 = 16 * t + 4 * g;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        s4 a;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a[j] = (short)aref<false>(R, ld, ni, nk, 16 * mt + el, k0 + j);
+        const s4 a = A.at4(16 * mt + el, k0);
 #pragma unroll
         for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], acc[mt][p], 0, 0, 0);
       }
@@ -218,54 +232,7 @@ __device__ __forceinline__ void contract_star(f4 (&acc)[MT][9], const RefT<Op>* 
   }
 }
 
-// One Cauchy-Kowalevski step: D(K+1) from D(K), output quantity by quantity.
-template <class Op, int N, int K, int RTI, int RTO>
-__device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&dout)[RTO][4][9],
-                                        const RefT<Op>* sK, const float* G, float lam, float mu, float rinv,
-                                        int el, int g) {
-  constexpr int B = nbasis(N), B1 = nbasis(N - 1);
-  constexpr int nin = nbasis(N - K), nout = nbasis(N - K - 1);
-  const float fk = -1.0f / float(K + 1);
-  auto body = [&](auto pc) {
-    constexpr int p = decltype(pc)::value;
-    f4 acc[RTO][1];
-#pragma unroll
-    for (int mt = 0; mt < RTO; ++mt) acc[mt][0] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      // z = (dt A*_d D(K))_p for the rows this lane holds
-      float z[RTI][4][1];
-#pragma unroll
-      for (int t = 0; t < RTI; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float ux, uy, uz;
-          flux_comp<p>(din[t][v], lam, mu, rinv, ux, uy, uz);
-          z[t][v][0] = G[3 * d + 0] * ux + G[3 * d + 1] * uy + G[3 * d + 2] * uz;
-        }
-      // A(m, l) = K^d[l][m]: stored block K^d[l < B][m < B1]
-      contract<Op, true, RTI, RTO, 1>(acc, sK + d * B * B1, B1, B1, B, z, nin, el, g);
-    }
-#pragma unroll
-    for (int mt = 0; mt < RTO; ++mt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 16 * mt + 4 * g + v;
-        dout[mt][v][p] = row < nout ? fk * acc[mt][0][v] : 0.0f;
-      }
-  };
-  body(std::integral_constant<int, 0>{});
-  body(std::integral_constant<int, 1>{});
-  body(std::integral_constant<int, 2>{});
-  body(std::integral_constant<int, 3>{});
-  body(std::integral_constant<int, 4>{});
-  body(std::integral_constant<int, 5>{});
-  body(std::integral_constant<int, 6>{});
-  body(std::integral_constant<int, 7>{});
-  body(std::integral_constant<int, 8>{});
-}
-
-// accumulate I~ += D(K+1)/(K+2)
+// accumulate J += w D
 template <int RT, int RTO>
 __device__ __forceinline__ void accum(float (&I)[RT][4][9], const float (&d)[RTO][4][9], float w) {
 #pragma unroll
@@ -291,47 +258,155 @@ __device__ __forceinline__ void store_deriv(float* dst, const float (&x)[RTX][4]
     }
 }
 
+// One Cauchy-Kowalevski step D(K+1) = fk sum_d (K^d)^T (D(K) (dt A*_d)^T) for the
+// output quantities [P0, P1); the star product of each input row is formed
+// lane-locally right before it enters the matrix cores.
+template <class Op, int N, int K, int RTI, int RTO, int P0 = 0, int P1 = 9>
+__device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&dout)[RTO][4][9],
+                                        const RefT<Op>* lds, const float* G, float lam, float mu, float rinv,
+                                        int el, int g, float fk) {
+  using L = Lay<Op, N>;
+  constexpr int nin = nbasis(N - K), nout = nbasis(N - K - 1);
+  constexpr int NP = P1 - P0;
+  f4 acc[RTO][NP];
+#pragma unroll
+  for (int mt = 0; mt < RTO; ++mt)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[mt][p] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if constexpr (std::is_same<Op, OpF32>::value) {
+      const View<float, L::ldK, true> A(lds + L::oK + d * L::B * L::ldK);  // A(m, l) = K^d[l][m]
+#pragma unroll
+      for (int t = 0; t < RTI; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (16 * t + v >= nin) continue;
+          float z[9];
+          apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z);
+          const int k = 16 * t + 4 * g + v;
+#pragma unroll
+          for (int mt = 0; mt < RTO; ++mt) {
+            const float af = A.at(16 * mt + el, k);
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+              acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, z[P0 + p], acc[mt][p], 0, 0, 0);
+          }
+        }
+    } else {
+      const View<unsigned short, L::ldT, false> A(lds + L::oT + d * L::B1 * L::ldT);  // (K^d)^T[m][l]
+#pragma unroll
+      for (int t = 0; t < RTI; ++t) {
+        if (16 * t >= nin) continue;
+        float z[4][9];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z[v]);
+        s4 bz[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) bz[p] = pack4(z[0][P0 + p], z[1][P0 + p], z[2][P0 + p], z[3][P0 + p]);
+        const int k0 = 16 * t + 4 * g;
+#pragma unroll
+        for (int mt = 0; mt < RTO; ++mt) {
+          const s4 af = A.at4(16 * mt + el, k0);
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+            acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bz[p], acc[mt][p], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < RTO; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * mt + 4 * g + v;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) dout[mt][v][P0 + p] = row < nout ? fk * acc[mt][p][v] : 0.0f;
+    }
+}
+
+// First CK step straight from Q in memory (group base Qg): the stress rows of
+// D1 read only the velocity columns of D0 and the velocity rows only the
+// stress columns, so D0 is brought in one half at a time.
+template <class Op, int N, int P0, int P1, int C0, int C1>
+__device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1))][4][9], const float* Qg,
+                                              int lane, const RefT<Op>* lds, const float* G, float lam, float mu,
+                                              float rinv, int el, int g, float* gd) {
+  constexpr int B = nbasis(N), RT = row_tiles(B), RT1 = row_tiles(nbasis(N - 1));
+  const GroupBuf qb(Qg, RT * 36 * 256, lane);
+  float din[RT][4][9];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const bool ok = 16 * t + 4 * g + v < B;
+#pragma unroll
+      for (int p = 0; p < 9; ++p)
+        din[t][v][p] = (p >= C0 && p < C1) ? (ok ? qb.ld((t * 4 + v) * 9 + p) : 0.0f) : 0.0f;
+    }
+  if (gd) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * t + 4 * g + v;
+        if (row >= B) continue;
+#pragma unroll
+        for (int p = C0; p < C1; ++p) gd[row * 9 + p] = din[t][v][p];
+      }
+  }
+  ck_step<Op, N, 0, RT, RT1, P0, P1>(din, d1, lds, G, lam, mu, rinv, el, g, -1.0f);
+}
+
 template <class Op, int N>
 struct CK {
-  // Runs the whole CK chain; I (holding D0 on entry) ends as I~.
-  __device__ static void run(float (&I)[row_tiles(nbasis(N))][4][9], const RefT<Op>* sK, const float* G, float lam,
-                             float mu, float rinv, int el, int g, float* gd) {
-    constexpr int R0 = row_tiles(nbasis(N)), R1 = row_tiles(nbasis(N - 1));
-    float d1[R1][4][9];
-    if (gd) store_deriv<N>(gd, I, g);
-    ck_step<Op, N, 0, R0, R1>(I, d1, sK, G, lam, mu, rinv, el, g);
-    if (gd) store_deriv<N>(gd + 1 * nbasis(N) * 9, d1, g);
-    accum(I, d1, 0.5f);
+  // J = sum_{k >= 1} Dk/(k+1) (rows below B1); I~ = Q + J.
+  __device__ static void run(float (&J)[row_tiles(nbasis(N - 1))][4][9], const float* Qg, int lane,
+                             const RefT<Op>* lds, const float* G, float lam, float mu, float rinv, int el, int g,
+                             float* gd) {
+    constexpr int B = nbasis(N);
+    constexpr int R1 = row_tiles(nbasis(N - 1));
+    ck_first_half<Op, N, 0, 6, 6, 9>(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
+    __builtin_amdgcn_sched_barrier(0);
+    ck_first_half<Op, N, 6, 9, 0, 6>(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
+    if (gd) store_deriv<N>(gd + 1 * B * 9, J, g);
+#pragma unroll
+    for (int t = 0; t < R1; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int p = 0; p < 9; ++p) J[t][v][p] *= 0.5f;  // J = D1/2
+    __builtin_amdgcn_sched_barrier(0);
     if constexpr (N >= 2) {
       constexpr int R2 = row_tiles(nbasis(N - 2));
       float d2[R2][4][9];
-      ck_step<Op, N, 1, R1, R2>(d1, d2, sK, G, lam, mu, rinv, el, g);
-      if (gd) store_deriv<N>(gd + 2 * nbasis(N) * 9, d2, g);
-      accum(I, d2, 1.0f / 3.0f);
+      ck_step<Op, N, 1, R1, R2>(J, d2, lds, G, lam, mu, rinv, el, g, -1.0f);  // input D1/2
+      if (gd) store_deriv<N>(gd + 2 * B * 9, d2, g);
+      accum(J, d2, 1.0f / 3.0f);
       if constexpr (N >= 3) {
         constexpr int R3 = row_tiles(nbasis(N - 3));
         float d3[R3][4][9];
-        ck_step<Op, N, 2, R2, R3>(d2, d3, sK, G, lam, mu, rinv, el, g);
-        if (gd) store_deriv<N>(gd + 3 * nbasis(N) * 9, d3, g);
-        accum(I, d3, 0.25f);
+        ck_step<Op, N, 2, R2, R3>(d2, d3, lds, G, lam, mu, rinv, el, g, -1.0f / 3.0f);
+        if (gd) store_deriv<N>(gd + 3 * B * 9, d3, g);
+        accum(J, d3, 0.25f);
         if constexpr (N >= 4) {
           constexpr int R4 = row_tiles(nbasis(N - 4));
           float d4[R4][4][9];
-          ck_step<Op, N, 3, R3, R4>(d3, d4, sK, G, lam, mu, rinv, el, g);
-          if (gd) store_deriv<N>(gd + 4 * nbasis(N) * 9, d4, g);
-          accum(I, d4, 0.2f);
+          ck_step<Op, N, 3, R3, R4>(d3, d4, lds, G, lam, mu, rinv, el, g, -0.25f);
+          if (gd) store_deriv<N>(gd + 4 * B * 9, d4, g);
+          accum(J, d4, 0.2f);
           if constexpr (N >= 5) {
             constexpr int R5 = row_tiles(nbasis(N - 5));
             float d5[R5][4][9];
-            ck_step<Op, N, 4, R4, R5>(d4, d5, sK, G, lam, mu, rinv, el, g);
-            if (gd) store_deriv<N>(gd + 5 * nbasis(N) * 9, d5, g);
-            accum(I, d5, 1.0f / 6.0f);
+            ck_step<Op, N, 4, R4, R5>(d4, d5, lds, G, lam, mu, rinv, el, g, -0.2f);
+            if (gd) store_deriv<N>(gd + 5 * B * 9, d5, g);
+            accum(J, d5, 1.0f / 6.0f);
             if constexpr (N >= 6) {
               constexpr int R6 = row_tiles(nbasis(N - 6));
               float d6[R6][4][9];
-              ck_step<Op, N, 5, R5, R6>(d5, d6, sK, G, lam, mu, rinv, el, g);
-              if (gd) store_deriv<N>(gd + 6 * nbasis(N) * 9, d6, g);
-              accum(I, d6, 1.0f / 7.0f);
+              ck_step<Op, N, 5, R5, R6>(d5, d6, lds, G, lam, mu, rinv, el, g, -1.0f / 6.0f);
+              if (gd) store_deriv<N>(gd + 6 * B * 9, d6, g);
+              accum(J, d6, 1.0f / 7.0f);
             }
           }
         }
@@ -340,233 +415,319 @@ struct CK {
   }
 };
 
+template <class Op>
+__device__ __forceinline__ void stage_ref(void* lds, const void* ref, int bytes, int nthreads) {
+  const uint4* src = reinterpret_cast<const uint4*>(ref);
+  uint4* dst = reinterpret_cast<uint4*>(lds);
+  for (int i = threadIdx.x; i < bytes / 16; i += nthreads) dst[i] = src[i];
+}
+
+// Predictor: persistent work-groups of W wavefronts; wavefront w of block b
+// handles the 16-element groups first + b*W + w, then strides by gridDim*W.
 template <class Op, int N, int W>
 __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, int64_t e1, int parity) {
-  using D = Dim<N>;
-  constexpr int B = D::B, Bf = D::Bf, B1 = D::B1, RT = D::RT, FT = D::FT, RT1 = D::RT1;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
+  using L = Lay<Op, N>;
+  constexpr int B = L::B, Bf = L::Bf, B1 = L::B1, RT = L::RT, FT = L::FT, RT1 = L::RT1;
   using R = RefT<Op>;
-  R* sK = reinterpret_cast<R*>(lds_raw);
-  R* sE = sK + D::nK;
-  R* sL = sE + D::nE;
-  {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.ref);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(lds_raw);
-    const int n32 = a.ref_bytes / 4;
-    for (int i = threadIdx.x; i < n32; i += 64 * W) dst[i] = src[i];
-  }
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const R* lds = reinterpret_cast<const R*>(lds_raw);
+  stage_ref<Op>(lds_raw, a.ref, L::bytes, 64 * W);
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, el = lane & 15, g = lane >> 4;
-  const int64_t grp = (e0 >> 4) + (int64_t)blockIdx.x * W + w;
-  if (grp > ((e1 - 1) >> 4)) return;
-  const int64_t e = grp * 16 + el;
-  const bool live = e >= e0 && e < e1;
-  const int64_t ec = live ? e : e0;
+  // the wavefront index is uniform across the wavefront: keep it (and every
+  // group base and buffer descriptor derived from it) in scalar registers
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int el = lane & 15, g = lane >> 4;
+  const int64_t gfirst = e0 >> 4, glast = (e1 - 1) >> 4;
+  for (int64_t grp = gfirst + (int64_t)blockIdx.x * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
+    const int64_t e = grp * 16 + el;
+    const bool live = e >= e0 && e < e1;
+    const int64_t ec = live ? e : e0;
+    float G[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) G[i] = a.G[ec * 9 + i];
+    const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
+    const float* Qg = a.Q + grp * (int64_t)(RT * 36 * 64);
+    const int gs = live ? a.gslot[e] : -1;
+    float* gd = gs >= 0 ? a.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
 
-  float G[9];
+    // J = sum_{k>=1} Dk/(k+1) is parked in memory (same fragment layout, one
+    // coalesced access per register) so that its registers are free for the
+    // face and volume phases; I~ = Q + J is streamed back from L2 there.
+    float* Jg = a.Jb + grp * (int64_t)(RT1 * 36 * 64);
+    {
+      float J[RT1][4][9];
+      CK<Op, N>::run(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
+      const GroupBuf jb(Jg, RT1 * 36 * 256, lane);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) G[i] = a.G[ec * 9 + i];
-  const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
-
-  // load Q (one coalesced 256-byte access per register)
-  float I[RT][4][9];
-  const float* Qg = a.Q + grp * (int64_t)(RT * 36 * 64);
+      for (int t = 0; t < RT1; ++t)
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const bool ok = 16 * t + 4 * g + v < B;
-#pragma unroll
-      for (int p = 0; p < 9; ++p) I[t][v][p] = ok ? Qg[((t * 4 + v) * 9 + p) * 64 + lane] : 0.0f;
+          for (int p = 0; p < 9; ++p) jb.st((t * 4 + v) * 9 + p, J[t][v][p]);
     }
+    __builtin_amdgcn_sched_barrier(0);
 
-  const int gs = live ? a.gslot[e] : -1;
-  float* gd = gs >= 0 ? a.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
-  CK<Op, N>::run(I, sK, G, lam, mu, rinv, el, g, gd);
+    f4 dq[RT][9];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
 
-  f4 dq[RT][9];
+    // rows of I~ = Q + J, read through laundered bases (one pair per contraction,
+    // so the reads are not merged across contractions and kept live)
+    auto itil_at = [&](const float* qp, const float* jp) {
+      const GroupBuf qb(qp, RT * 36 * 256, lane), jb(jp, RT1 * 36 * 256, lane);
+      return [=](int t, int v, float (&b)[9]) {
+        const bool ok = 16 * t + 4 * g + v < B;
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
-#pragma unroll
-    for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int p = 0; p < 9; ++p) {
+          float x = ok ? qb.ld((t * 4 + v) * 9 + p) : 0.0f;
+          if (t < RT1) x += jb.ld((t < RT1 ? t * 4 + v : 0) * 9 + p);
+          b[p] = x;
+        }
+      };
+    };
 
-  // volume: dq += sum_d K^d (I~ (dt A*_d)^T), rows of I~ below B1
+    // faces: traces at the nodes, hand-over, own-trace flux, lift
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-    contract_star<Op, RT, RT>(dq, sK + d * B * B1, B1, B, B1, I, B1, G + 3 * d, lam, mu, rinv, el, g);
-
-  // faces: traces at the nodes, hand-over, own-trace flux, lift
+    for (int f = 0; f < 4; ++f) {
+      f4 va[FT][9];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    f4 va[FT][9];
+      for (int t = 0; t < FT; ++t)
 #pragma unroll
-    for (int t = 0; t < FT; ++t)
-#pragma unroll
-      for (int p = 0; p < 9; ++p) va[t][p] = f4{0.f, 0.f, 0.f, 0.f};
-    contract<Op, false, RT, FT, 9>(va, sE + f * Bf * B, B, Bf, B, I, B, el, g);
-    float V[FT][4][9];
-#pragma unroll
-    for (int t = 0; t < FT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const bool ok = 16 * t + 4 * g + v < Bf;
-#pragma unroll
-        for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? va[t][p][v] : 0.0f;
-      }
-    const int md = live ? a.mode[ec * 4 + f] : 0;
-    if (md != 0) {
-      const int32_t tg = a.tgt[ec * 4 + f];
-      const int h = a.hperm[ec * 4 + f];
+        for (int p = 0; p < 9; ++p) va[t][p] = f4{0.f, 0.f, 0.f, 0.f};
+      const View<R, L::ldE, false> AE(lds + L::oE + f * Bf * L::ldE);
+      contract_fn<Op, View<R, L::ldE, false>, RT, FT>(va, AE, B, el, g,
+                                                      itil_at(Qg, Jg));
+      float V[FT][4][9];
 #pragma unroll
       for (int t = 0; t < FT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int node = 16 * t + 4 * g + v;
-          if (node >= Bf) continue;
-          const int mr = a.pinv[h * Bf + node];
+          const bool ok = 16 * t + 4 * g + v < Bf;
+#pragma unroll
+          for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? va[t][p][v] : 0.0f;
+        }
+      const int md = live ? a.mode[ec * 4 + f] : 0;
+      if (md != 0) {
+        const int32_t tg = a.tgt[ec * 4 + f];
+        const int h = a.hperm[ec * 4 + f];
+#pragma unroll
+        for (int t = 0; t < FT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int node = 16 * t + 4 * g + v;
+            if (node >= Bf) continue;
+            const int mr = a.pinv[h * Bf + node];
+#pragma unroll
+            for (int p = 0; p < 9; ++p) {
+              float* dst = a.In + inidx(tg >> 2, tg & 3, mr, p, FT);
+              if (md == 1) *dst = V[t][v][p];
+              else *dst = parity ? *dst + 0.5f * V[t][v][p] : 0.5f * V[t][v][p];
+            }
+          }
+      }
+      float c[11];
+#pragma unroll
+      for (int i = 0; i < 11; ++i) c[i] = a.RCm[(ec * 4 + f) * 12 + i];
+#pragma unroll
+      for (int t = 0; t < FT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float out[9];
+          node_flux(c, lam, mu, rinv, V[t][v], out);
+#pragma unroll
+          for (int p = 0; p < 9; ++p) V[t][v][p] = -out[p];
+        }
+      const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL);
+      contract_fn<Op, View<R, L::ldL, false>, FT, RT>(dq, AL, Bf, el, g,
+                                                      [&](int t, int v, float (&b)[9]) {
+#pragma unroll
+                                                        for (int p = 0; p < 9; ++p) b[p] = V[t][v][p];
+                                                      });
+#if SEIS_FACE_BARRIER
+      __builtin_amdgcn_sched_barrier(0);
+#endif
+    }
+
+    // volume: dq += sum_d K^d (I~ (dt A*_d)^T) over the rows of I~ below B1
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const View<R, L::ldK, false> AK(lds + L::oK + d * B * L::ldK);
+      auto itil = itil_at(Qg, Jg);
+      contract_fn<Op, View<R, L::ldK, false>, RT1, RT>(dq, AK, B1, el, g, [&](int t, int v, float (&b)[9]) {
+        float x[9];
+        itil(t, v, x);
+        apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x, b);
+        if (16 * t + 4 * g + v >= B1)
+#pragma unroll
+          for (int p = 0; p < 9; ++p) b[p] = 0.0f;
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    }
+
+    {
+      // Q += dq for live elements and rows below B
+      const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (!live || 16 * t + 4 * g + v >= B) continue;
 #pragma unroll
           for (int p = 0; p < 9; ++p) {
-            float* dst = a.In + inidx(tg >> 2, tg & 3, mr, p, FT);
-            if (md == 1) *dst = V[t][v][p];
-            else *dst = parity ? *dst + 0.5f * V[t][v][p] : 0.5f * V[t][v][p];
+            const int r = (t * 4 + v) * 9 + p;
+            qb.st(r, qb.ld(r) + dq[t][p][v]);
           }
         }
     }
-    float c[11];
-#pragma unroll
-    for (int i = 0; i < 11; ++i) c[i] = a.RCm[(ec * 4 + f) * 12 + i];
-#pragma unroll
-    for (int t = 0; t < FT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float out[9];
-        node_flux(c, lam, mu, rinv, V[t][v], out);
-#pragma unroll
-        for (int p = 0; p < 9; ++p) V[t][v][p] = -out[p];
-      }
-    contract<Op, false, FT, RT, 9>(dq, sL + f * B * Bf, Bf, B, Bf, V, Bf, el, g);
-  }
-
-  // Q += dq
-  if (live) {
-    float* Qw = a.Q + grp * (int64_t)(RT * 36 * 64);
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (16 * t + 4 * g + v >= B) continue;
-#pragma unroll
-        for (int p = 0; p < 9; ++p) {
-          const int idx = ((t * 4 + v) * 9 + p) * 64 + lane;
-          Qw[idx] += dq[t][p][v];
-        }
-      }
   }
 }
 
+#ifndef SEIS_CORR_SPLIT
+#define SEIS_CORR_SPLIT 2
+#endif
+#ifndef SEIS_FACE_BARRIER
+#define SEIS_FACE_BARRIER 1
+#endif
+
+// Corrector: Q -= sum_f L_f flux(neighbour trace of face f). The output rows
+// are produced in SEIS_CORR_SPLIT passes (the face fluxes are recomputed per
+// pass from the inbox, which is L2-resident by then) so that the accumulators
+// of one pass leave room for two wavefronts per SIMD.
 template <class Op, int N, int W>
 __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, int64_t e1) {
-  using D = Dim<N>;
-  constexpr int B = D::B, Bf = D::Bf, RT = D::RT, FT = D::FT;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
+  using L = Lay<Op, N>;
+  constexpr int B = L::B, Bf = L::Bf, RT = L::RT, FT = L::FT;
+  constexpr int NS = (SEIS_CORR_SPLIT > RT) ? RT : SEIS_CORR_SPLIT;
+  constexpr int MH = (RT + NS - 1) / NS;  // row tiles per pass
   using R = RefT<Op>;
-  R* sL = reinterpret_cast<R*>(lds_raw);
-  {
-    // only the lifts are needed: they sit after K and E in the reference block
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(
-        reinterpret_cast<const unsigned char*>(a.ref) + (D::nK + D::nE) * sizeof(R));
-    uint32_t* dst = reinterpret_cast<uint32_t*>(lds_raw);
-    const int n32 = (D::nL * (int)sizeof(R) + 3) / 4;
-    for (int i = threadIdx.x; i < n32; i += 64 * W) dst[i] = src[i];
-  }
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const R* lds = reinterpret_cast<const R*>(lds_raw);
+  stage_ref<Op>(lds_raw, a.ref, L::bytes, 64 * W);
   __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, el = lane & 15, g = lane >> 4;
-  const int64_t grp = (e0 >> 4) + (int64_t)blockIdx.x * W + w;
-  if (grp > ((e1 - 1) >> 4)) return;
-  const int64_t e = grp * 16 + el;
-  const bool live = e >= e0 && e < e1;
-  const int64_t ec = live ? e : e0;
-  const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
-
-  f4 dq[RT][9];
+  // the wavefront index is uniform across the wavefront: keep it (and every
+  // group base and buffer descriptor derived from it) in scalar registers
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int el = lane & 15, g = lane >> 4;
+  const int64_t gfirst = e0 >> 4, glast = (e1 - 1) >> 4;
+  for (int64_t grp = gfirst + (int64_t)blockIdx.x * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
+    const int64_t e = grp * 16 + el;
+    const bool live = e >= e0 && e < e1;
+    const int64_t ec = live ? e : e0;
+    const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
+    for (int h = 0; h < NS; ++h) {
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int t0 = h * MH;
+      f4 dq[MH][9];
 #pragma unroll
-    for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
-
+      for (int t = 0; t < MH; ++t)
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    const float* Ig = a.In + ((grp * 4 + f) * (int64_t)(FT * 36 * 64));
-    float c[11];
+        for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < 11; ++i) c[i] = a.RCp[(ec * 4 + f) * 12 + i];
-    float V[FT][4][9];
+      for (int f = 0; f < 4; ++f) {
+        const GroupBuf ib(a.In + ((grp * 4 + f) * (int64_t)(FT * 36 * 64)), FT * 36 * 256, lane);
+        float c[11];
 #pragma unroll
-    for (int t = 0; t < FT; ++t)
+        for (int i = 0; i < 11; ++i) c[i] = a.RCp[(ec * 4 + f) * 12 + i];
+        float V[FT][4][9];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float in[9], out[9];
+        for (int t = 0; t < FT; ++t)
 #pragma unroll
-        for (int p = 0; p < 9; ++p) in[p] = Ig[((t * 4 + v) * 9 + p) * 64 + lane];
-        node_flux(c, lam, mu, rinv, in, out);
-        const bool ok = 16 * t + 4 * g + v < Bf;
+          for (int v = 0; v < 4; ++v) {
+            float in[9], out[9];
 #pragma unroll
-        for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? -out[p] : 0.0f;
+            for (int p = 0; p < 9; ++p) in[p] = ib.ld((t * 4 + v) * 9 + p);
+            node_flux(c, lam, mu, rinv, in, out);
+            const bool ok = 16 * t + 4 * g + v < Bf;
+#pragma unroll
+            for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? -out[p] : 0.0f;
+          }
+        const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL + t0 * 16 * L::ldL);
+        contract_fn<Op, View<R, L::ldL, false>, FT, MH>(dq, AL, Bf, el, g,
+                                                        [&](int t, int v, float (&b)[9]) {
+#pragma unroll
+                                                          for (int p = 0; p < 9; ++p) b[p] = V[t][v][p];
+                                                        });
+#if SEIS_FACE_BARRIER
+        __builtin_amdgcn_sched_barrier(0);
+#endif
       }
-    contract<Op, false, FT, RT, 9>(dq, sL + f * B * Bf, Bf, B, Bf, V, Bf, el, g);
-  }
-  if (live) {
-    float* Qw = a.Q + grp * (int64_t)(RT * 36 * 64);
+      const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+      for (int tt = 0; tt < MH; ++tt) {
+        const int t = t0 + tt;
+        if (t >= RT) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (16 * t + 4 * g + v >= B) continue;
+        for (int v = 0; v < 4; ++v) {
+          if (!live || 16 * t + 4 * g + v >= B) continue;
 #pragma unroll
-        for (int p = 0; p < 9; ++p) {
-          const int idx = ((t * 4 + v) * 9 + p) * 64 + lane;
-          Qw[idx] += dq[t][p][v];
+          for (int p = 0; p < 9; ++p) {
+            const int r = (t * 4 + v) * 9 + p;
+            qb.st(r, qb.ld(r) + dq[tt][p][v]);
+          }
         }
       }
+    }
   }
 }
 
-template <class Op, int N>
-int ref_bytes() {
-  return (Dim<N>::nK + Dim<N>::nE + Dim<N>::nL) * (int)sizeof(RefT<Op>);
+int g_num_cus = 0;
+
+int num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      g_num_cus = prop.multiProcessorCount;
+    if (g_num_cus <= 0) g_num_cus = 256;
+  }
+  return g_num_cus;
+}
+
+// Work-groups per launch: one per group of W 16-element groups, or, when the
+// SEIS_WG_PER_CU environment variable is set to k > 0, at most k per compute
+// unit (persistent work-groups striding over the groups).
+int g_wg_per_cu = -1;
+unsigned grid_size(int64_t ngroups, int W, int lds_bytes) {
+  if (g_wg_per_cu < 0) {
+    const char* e = std::getenv("SEIS_WG_PER_CU");
+    g_wg_per_cu = e ? std::max(0, std::atoi(e)) : 0;
+  }
+  const int64_t full = (ngroups + W - 1) / W;
+  if (g_wg_per_cu == 0) return (unsigned)full;
+  (void)lds_bytes;
+  return (unsigned)std::min<int64_t>(full, (int64_t)num_cus() * g_wg_per_cu);
+}
+
+template <class KernelPtr>
+hipError_t prep(KernelPtr k, int lds) {
+  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 template <class Op, int N, int W>
 hipError_t launch_pred(const TArgs& a, int64_t e0, int64_t e1, int parity, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
+  using L = Lay<Op, N>;
   const int64_t ng = ((e1 - 1) >> 4) - (e0 >> 4) + 1;
-  const unsigned grid = (unsigned)((ng + W - 1) / W);
-  const int lds = (ref_bytes<Op, N>() + 3) / 4 * 4;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t st = hipFuncSetAttribute((const void*)k_predict_tuned<Op, N, W>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (st != hipSuccess) return st;
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_predict_tuned<Op, N, W>), dim3(grid), dim3(64 * W), lds, s, a, e0, e1, parity);
+  const unsigned grid = grid_size(ng, W, L::bytes);
+  static hipError_t attr = prep(k_predict_tuned<Op, N, W>, L::bytes);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((k_predict_tuned<Op, N, W>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1, parity);
   return hipGetLastError();
 }
 
 template <class Op, int N, int W>
 hipError_t launch_corr(const TArgs& a, int64_t e0, int64_t e1, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
+  using L = Lay<Op, N>;
   const int64_t ng = ((e1 - 1) >> 4) - (e0 >> 4) + 1;
-  const unsigned grid = (unsigned)((ng + W - 1) / W);
-  const int lds = (Dim<N>::nL * (int)sizeof(RefT<Op>) + 3) / 4 * 4;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t st = hipFuncSetAttribute((const void*)k_correct_tuned<Op, N, W>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (st != hipSuccess) return st;
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_correct_tuned<Op, N, W>), dim3(grid), dim3(64 * W), lds, s, a, e0, e1);
+  const unsigned grid = grid_size(ng, W, L::bytes);
+  static hipError_t attr = prep(k_correct_tuned<Op, N, W>, L::bytes);
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((k_correct_tuned<Op, N, W>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1);
   return hipGetLastError();
 }
 
@@ -574,11 +735,11 @@ template <class Op>
 hipError_t pred_dispatch(int N, int W, const TArgs& a, int64_t e0, int64_t e1, int parity, hipStream_t s) {
 #define SEIS_P(NN, WW) \
   if (N == NN && W == WW) return launch_pred<Op, NN, WW>(a, e0, e1, parity, s);
-  SEIS_P(2, 1) SEIS_P(2, 2) SEIS_P(2, 4)
-  SEIS_P(3, 1) SEIS_P(3, 2) SEIS_P(3, 4)
-  SEIS_P(4, 1) SEIS_P(4, 2) SEIS_P(4, 4)
-  SEIS_P(5, 1) SEIS_P(5, 2) SEIS_P(5, 4)
-  SEIS_P(6, 1) SEIS_P(6, 2) SEIS_P(6, 4)
+  SEIS_P(2, 2) SEIS_P(2, 4)
+  SEIS_P(3, 2) SEIS_P(3, 4)
+  SEIS_P(4, 2) SEIS_P(4, 4)
+  SEIS_P(5, 2) SEIS_P(5, 4)
+  SEIS_P(6, 2) SEIS_P(6, 4)
 #undef SEIS_P
   return hipErrorInvalidValue;
 }
@@ -587,11 +748,11 @@ template <class Op>
 hipError_t corr_dispatch(int N, int W, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s) {
 #define SEIS_C(NN, WW) \
   if (N == NN && W == WW) return launch_corr<Op, NN, WW>(a, e0, e1, s);
-  SEIS_C(2, 1) SEIS_C(2, 2) SEIS_C(2, 4)
-  SEIS_C(3, 1) SEIS_C(3, 2) SEIS_C(3, 4)
-  SEIS_C(4, 1) SEIS_C(4, 2) SEIS_C(4, 4)
-  SEIS_C(5, 1) SEIS_C(5, 2) SEIS_C(5, 4)
-  SEIS_C(6, 1) SEIS_C(6, 2) SEIS_C(6, 4)
+  SEIS_C(2, 2) SEIS_C(2, 4)
+  SEIS_C(3, 2) SEIS_C(3, 4)
+  SEIS_C(4, 2) SEIS_C(4, 4)
+  SEIS_C(5, 2) SEIS_C(5, 4)
+  SEIS_C(6, 2) SEIS_C(6, 4)
 #undef SEIS_C
   return hipErrorInvalidValue;
 }
@@ -611,6 +772,39 @@ hipError_t upload(std::vector<void*>& owned, int64_t& bytes, X** dst, const std:
   return hipMemcpy(p, tmp.data(), tmp.size() * sizeof(X), hipMemcpyHostToDevice);
 }
 
+// Host image of the LDS reference block (same layout as Lay<Op, N>).
+template <class Op, int N>
+std::vector<double> ref_image(const Model& M) {
+  using L = Lay<Op, N>;
+  const int B = L::B, Bf = L::Bf, B1 = L::B1;
+  std::vector<double> r(L::total, 0.0);
+  for (int d = 0; d < 3; ++d)
+    for (int k = 0; k < B; ++k)
+      for (int l = 0; l < B1; ++l) {
+        const double v = M.ref.K[(d * B + k) * B + l];
+        r[L::oK + (d * B + k) * L::ldK + l] = v;
+        if (L::BF) r[L::oT + (d * B1 + l) * L::ldT + k] = v;
+      }
+  for (int f = 0; f < 4; ++f)
+    for (int m = 0; m < Bf; ++m)
+      for (int k = 0; k < B; ++k) {
+        r[L::oE + (f * Bf + m) * L::ldE + k] = M.ref.E[(f * Bf + m) * B + k];
+        r[L::oL + (f * B + k) * L::ldL + m] = M.ref.L[(f * B + k) * Bf + m];
+      }
+  return r;
+}
+
+template <class Op>
+std::vector<double> ref_image_n(const Model& M, int& bytes) {
+  switch (M.N) {
+    case 2: bytes = Lay<Op, 2>::bytes; return ref_image<Op, 2>(M);
+    case 3: bytes = Lay<Op, 3>::bytes; return ref_image<Op, 3>(M);
+    case 4: bytes = Lay<Op, 4>::bytes; return ref_image<Op, 4>(M);
+    case 5: bytes = Lay<Op, 5>::bytes; return ref_image<Op, 5>(M);
+    default: bytes = Lay<Op, 6>::bytes; return ref_image<Op, 6>(M);
+  }
+}
+
 }  // namespace
 
 hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevData<double>& d64,
@@ -620,8 +814,7 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   t.d64 = d64;
   t.d32 = d32;
   t.iface_start = M.iface_start;
-  t.waves = tile > 0 ? std::max(1, std::min(4, tile / 16)) : 4;
-  if (t.waves == 3) t.waves = 2;
+  t.waves = (tile > 0 && tile <= 32) ? 2 : 4;
   if (precision == 0) {  // FP64 runs the plain kernels
     t.ready = 1;
     return hipSuccess;
@@ -636,37 +829,51 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   a.hperm = d32.hperm;
   a.gslot = d32.gslot;
   a.gD = d32.gD;
-  float *rcm, *rcp;
+  {
+    const int RT1 = row_tiles(n_basis(M.N - 1));
+    const int64_t nJ = ((M.E + 15) >> 4) * RT1 * 36 * 64;
+    void* pj = nullptr;
+    hipError_t sj = hipMalloc(&pj, nJ * sizeof(float));
+    if (sj != hipSuccess) return sj;
+    owned.push_back(pj);
+    bytes += nJ * int64_t(sizeof(float));
+    a.Jb = static_cast<float*>(pj);
+  }
+  // pointwise flux coefficients: filled by the operator assembly
+  float* rc[2] = {nullptr, nullptr};
+  for (int i = 0; i < 2; ++i) {
+    void* p = nullptr;
+    const int64_t n = M.E * 4 * 12;
+    hipError_t sa = hipMalloc(&p, n * sizeof(float));
+    if (sa != hipSuccess) return sa;
+    owned.push_back(p);
+    bytes += n * int64_t(sizeof(float));
+    rc[i] = static_cast<float*>(p);
+  }
+  float *rcm = rc[0], *rcp = rc[1];
   int32_t* pinv;
-  hipError_t st = upload(owned, bytes, &rcm, M.RCm);
-  if (st == hipSuccess) st = upload(owned, bytes, &rcp, M.RCp);
-  if (st == hipSuccess) st = upload(owned, bytes, &pinv, M.ref.pinv);
+  hipError_t st = upload(owned, bytes, &pinv, M.ref.pinv);
   if (st != hipSuccess) return st;
   a.RCm = rcm;
   a.RCp = rcp;
   a.pinv = pinv;
-  // reference block: K^d[k < B][l < B1] for d = 0..2, E_f, L_f
-  const int B = M.B, Bf = M.Bf, B1 = n_basis(M.N - 1);
-  std::vector<double> ref;
-  for (int d = 0; d < 3; ++d)
-    for (int k = 0; k < B; ++k)
-      for (int l = 0; l < B1; ++l) ref.push_back(M.ref.K[(d * B + k) * B + l]);
-  ref.insert(ref.end(), M.ref.E.begin(), M.ref.E.end());
-  ref.insert(ref.end(), M.ref.L.begin(), M.ref.L.end());
+  // LDS image of the reference matrices (layout of Lay<Op, N>), padded to 16 bytes
+  int lbytes = 0;
   if (precision == 1) {
+    std::vector<double> ref = ref_image_n<OpF32>(M, lbytes);
+    ref.resize(lbytes / 4, 0.0);
     float* r;
     st = upload(owned, bytes, &r, ref);
     a.ref = r;
-    a.ref_bytes = int(ref.size() * sizeof(float));
   } else {
-    std::vector<unsigned short> rb(ref.size());
-    for (size_t i = 0; i < ref.size(); ++i) rb[i] = f2bf((float)ref[i]);
-    if (rb.size() % 2) rb.push_back(0);
+    std::vector<double> ref = ref_image_n<OpBF16>(M, lbytes);
+    std::vector<unsigned short> rb(lbytes / 2, 0);
+    for (size_t i = 0; i < ref.size() && i < rb.size(); ++i) rb[i] = f2bf((float)ref[i]);
     unsigned short* r;
     st = upload(owned, bytes, &r, rb);
     a.ref = r;
-    a.ref_bytes = int(rb.size() * sizeof(unsigned short));
   }
+  a.ref_bytes = lbytes;
   if (st != hipSuccess) return st;
   t.ready = 1;
   return hipSuccess;

@@ -43,7 +43,7 @@ class Materials_t(C.Structure):
 
 class Options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("kernel", C.c_int), ("cfl", C.c_double), ("g", C.c_double),
-                ("max_clusters", C.c_int), ("stream", C.c_void_p), ("tile", C.c_int)]
+                ("max_clusters", C.c_int), ("stream", C.c_void_p), ("tile", C.c_int), ("graph", C.c_int)]
 
 
 class Info_t(C.Structure):
@@ -103,7 +103,7 @@ class Solver:
     """One library handle (seis_setup ... seis_destroy)."""
 
     def __init__(self, xyz, tet, face_kind, period, rho, lam, mu, order, *, precision="fp64",
-                 kernel="tuned", cfl=0.35, g=9.81, max_clusters=1, stream=None, tile=0):
+                 kernel="tuned", cfl=0.35, g=9.81, max_clusters=1, stream=None, tile=0, graph=False):
         lib = load_library()
         self._lib = lib
         self._keep = [np.ascontiguousarray(xyz, dtype=np.float64), np.ascontiguousarray(tet, dtype=np.int64),
@@ -122,6 +122,7 @@ class Solver:
         opt.max_clusters = max_clusters
         opt.stream = stream
         opt.tile = tile
+        opt.graph = 1 if graph else 0
         h = C.c_void_p()
         rc = lib.seis_setup(C.byref(mesh), C.byref(mats), int(order), C.byref(opt), C.byref(h))
         if rc != 0:
@@ -178,10 +179,12 @@ class Solver:
     def sync(self):
         self._check(self._lib.seis_sync(self._h))
 
-    def read(self):
-        d = np.empty((self.E, self.B, 9))
-        e = np.empty((self.n_gravity_faces, self.nq))
-        self._check(self._lib.seis_read(self._h, _ptr(d, C.c_double), _ptr(e, C.c_double)))
+    def read(self, dofs=True, eta=True):
+        """(dofs [E][B][9], eta [F_g][(N+1)^2]) in FP64; a part not asked for is None."""
+        d = np.empty((self.E, self.B, 9)) if dofs else None
+        e = np.empty((self.n_gravity_faces, self.nq)) if eta else None
+        self._check(self._lib.seis_read(self._h, None if d is None else _ptr(d, C.c_double),
+                                        None if e is None else _ptr(e, C.c_double)))
         return d, e
 
     def read_elements(self, ids):
