@@ -192,35 +192,58 @@ template <class Op, class V>
 __device__ __forceinline__ void mma_slice(f4& acc, const V& A, int i, int k, float b);
 
 // acc[mt][p] += sum_k A(16 mt + el, k) X[k][p]; X rows produced by rowfn(t, v, b[9])
-// for the input rows k < nrows (rows 16t + 4g + v of this lane).
-template <class Op, class V, int NT, int MT, class RowFn>
+// for the input rows k < nrows (rows 16t + 4g + v of this lane). With PIPE the
+// rows come from memory: the next row (FP32) or row tile (BF16) is requested
+// before the products of the current one, and a scheduling barrier per row
+// keeps the compiler from hoisting every load of the loop (which would need a
+// register per load in flight).
+template <class Op, class V, int NT, int MT, bool PIPE = false, class RowFn>
 __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nrows, int el, int g, RowFn rowfn) {
   if constexpr (std::is_same<Op, OpF32>::value) {
+    float b[2][9];
+    if constexpr (PIPE) rowfn(0, 0, b[0]);
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (16 * t + v >= nrows) continue;
-        float b[9];
-        rowfn(t, v, b);
-        const int k = 16 * t + 4 * g + v;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const float a = A.at(16 * mt + el, k);
-#pragma unroll
-          for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[p], acc[mt][p], 0, 0, 0);
-        }
+    for (int i = 0; i < 4 * NT; ++i) {
+      const int t = i >> 2, v = i & 3;
+      if (16 * t + v >= nrows) continue;
+      float(&cur)[9] = b[i & 1];
+      if constexpr (PIPE) {
+        const int tn = (i + 1) >> 2, vn = (i + 1) & 3;
+        if (i + 1 < 4 * NT && 16 * tn + vn < nrows) rowfn(tn, vn, b[(i + 1) & 1]);
+      } else {
+        rowfn(t, v, cur);
       }
+      const int k = 16 * t + 4 * g + v;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const float a = A.at(16 * mt + el, k);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, cur[p], acc[mt][p], 0, 0, 0);
+      }
+      if constexpr (PIPE) __builtin_amdgcn_sched_barrier(0);
+    }
   } else {
+    float bv[2][4][9];
+    if constexpr (PIPE) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rowfn(0, v, bv[0][v]);
+    }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (16 * t >= nrows) continue;
-      float bv[4][9];
+      float(&cur)[4][9] = bv[t & 1];
+      if constexpr (PIPE) {
+        if (t + 1 < NT && 16 * (t + 1) < nrows) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) rowfn(t, v, bv[v]);
+          for (int v = 0; v < 4; ++v) rowfn(t + 1, v, bv[(t + 1) & 1][v]);
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rowfn(t, v, cur[v]);
+      }
       s4 b[9];
 #pragma unroll
-      for (int p = 0; p < 9; ++p) b[p] = pack4(bv[0][p], bv[1][p], bv[2][p], bv[3][p]);
+      for (int p = 0; p < 9; ++p) b[p] = pack4(cur[0][p], cur[1][p], cur[2][p], cur[3][p]);
       const int k0 = 16 * t + 4 * g;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -228,6 +251,7 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
 #pragma unroll
         for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], acc[mt][p], 0, 0, 0);
       }
+      if constexpr (PIPE) __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -361,7 +385,7 @@ __device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1
 template <class Op, int N>
 struct CK {
   // J = sum_{k >= 1} Dk/(k+1) (rows below B1); I~ = Q + J.
-  __device__ static void run(float (&J)[row_tiles(nbasis(N - 1))][4][9], const float* Qg, int lane,
+  __device__ static __forceinline__ void run(float (&J)[row_tiles(nbasis(N - 1))][4][9], const float* Qg, int lane,
                              const RefT<Op>* lds, const float* G, float lam, float mu, float rinv, int el, int g,
                              float* gd) {
     constexpr int B = nbasis(N);
@@ -415,6 +439,85 @@ struct CK {
   }
 };
 
+// dq[mt][p] += sum_d sum_l K^d(16 mt + el, l) (I~_l (dt A*_d)^T)_p over the rows
+// l < B1 of I~ (rows produced by rowfn from memory), each row read once for
+// all three d; software-pipelined like contract_fn.
+template <class Op, int N, class RowFn>
+__device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const RefT<Op>* lds, RowFn rowfn,
+                                       const float* G, float lam, float mu, float rinv, int el, int g) {
+  using L = Lay<Op, N>;
+  constexpr int B = L::B, B1 = L::B1, RT = L::RT, RT1 = L::RT1;
+  using R = RefT<Op>;
+  const View<R, L::ldK, false> A0(lds + L::oK), A1(lds + L::oK + B * L::ldK), A2(lds + L::oK + 2 * B * L::ldK);
+  if constexpr (std::is_same<Op, OpF32>::value) {
+    float xb[2][9];
+    rowfn(0, 0, xb[0]);
+#pragma unroll
+    for (int i = 0; i < 4 * RT1; ++i) {
+      const int t = i >> 2, v = i & 3;
+      if (16 * t + v >= B1) continue;
+      const int tn = (i + 1) >> 2, vn = (i + 1) & 3;
+      if (i + 1 < 4 * RT1 && 16 * tn + vn < B1) rowfn(tn, vn, xb[(i + 1) & 1]);
+      const float(&x)[9] = xb[i & 1];
+      const bool ok = 16 * t + 4 * g + v < B1;
+      float z[3][9];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x, z[d]);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) z[d][p] = ok ? z[d][p] : 0.0f;
+      }
+      const int k = 16 * t + 4 * g + v;
+#pragma unroll
+      for (int mt = 0; mt < RT; ++mt) {
+        const float a0 = A0.at(16 * mt + el, k), a1 = A1.at(16 * mt + el, k), a2 = A2.at(16 * mt + el, k);
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+          dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, z[0][p], dq[mt][p], 0, 0, 0);
+          dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, z[1][p], dq[mt][p], 0, 0, 0);
+          dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, z[2][p], dq[mt][p], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  } else {
+    float xb[2][4][9];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rowfn(0, v, xb[0][v]);
+#pragma unroll
+    for (int t = 0; t < RT1; ++t) {
+      if (16 * t >= B1) continue;
+      if (t + 1 < RT1 && 16 * (t + 1) < B1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rowfn(t + 1, v, xb[(t + 1) & 1][v]);
+      }
+      const int k0 = 16 * t + 4 * g;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float z[4][9];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool ok = 16 * t + 4 * g + v < B1;
+          apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, xb[t & 1][v], z[v]);
+#pragma unroll
+          for (int p = 0; p < 9; ++p) z[v][p] = ok ? z[v][p] : 0.0f;
+        }
+        s4 b[9];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) b[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
+        const View<R, L::ldK, false>& A = d == 0 ? A0 : (d == 1 ? A1 : A2);
+#pragma unroll
+        for (int mt = 0; mt < RT; ++mt) {
+          const s4 a = A.at4(16 * mt + el, k0);
+#pragma unroll
+          for (int p = 0; p < 9; ++p) dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], dq[mt][p], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 template <class Op>
 __device__ __forceinline__ void stage_ref(void* lds, const void* ref, int bytes, int nthreads) {
   const uint4* src = reinterpret_cast<const uint4*>(ref);
@@ -450,20 +553,28 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     const int gs = live ? a.gslot[e] : -1;
     float* gd = gs >= 0 ? a.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
 
-    // J = sum_{k>=1} Dk/(k+1) is parked in memory (same fragment layout, one
-    // coalesced access per register) so that its registers are free for the
-    // face and volume phases; I~ = Q + J is streamed back from L2 there.
-    float* Jg = a.Jb + grp * (int64_t)(RT1 * 36 * 64);
+    // I~ = Q + J (J = sum_{k>=1} Dk/(k+1)) is parked in memory in the same
+    // fragment layout (one coalesced access per register) so that the CK
+    // registers are free for the face and volume phases, which stream I~
+    // back (mostly from L2).
+    float* Ig = a.Ib + grp * (int64_t)(RT * 36 * 64);
     {
       float J[RT1][4][9];
       CK<Op, N>::run(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
-      const GroupBuf jb(Jg, RT1 * 36 * 256, lane);
+      const GroupBuf qb(Qg, RT * 36 * 256, lane), ib(Ig, RT * 36 * 256, lane);
 #pragma unroll
-      for (int t = 0; t < RT1; ++t)
+      for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 4; ++v) {
+          const bool ok = 16 * t + 4 * g + v < B;
 #pragma unroll
-          for (int p = 0; p < 9; ++p) jb.st((t * 4 + v) * 9 + p, J[t][v][p]);
+          for (int p = 0; p < 9; ++p) {
+            const int r = (t * 4 + v) * 9 + p;
+            float x = ok ? qb.ld(r) : 0.0f;
+            if (t < RT1) x += J[t < RT1 ? t : 0][v][p];
+            ib.st(r, x);
+          }
+        }
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -473,23 +584,19 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
       for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // rows of I~ = Q + J, read through laundered bases (one pair per contraction,
-    // so the reads are not merged across contractions and kept live)
-    auto itil_at = [&](const float* qp, const float* jp) {
-      const GroupBuf qb(qp, RT * 36 * 256, lane), jb(jp, RT1 * 36 * 256, lane);
+    // rows of I~, read through a laundered base (one per contraction, so the
+    // reads are not merged across contractions and kept live)
+    auto itil_at = [&](const float* ip) {
+      const GroupBuf ib(ip, RT * 36 * 256, lane);
       return [=](int t, int v, float (&b)[9]) {
-        const bool ok = 16 * t + 4 * g + v < B;
 #pragma unroll
-        for (int p = 0; p < 9; ++p) {
-          float x = ok ? qb.ld((t * 4 + v) * 9 + p) : 0.0f;
-          if (t < RT1) x += jb.ld((t < RT1 ? t * 4 + v : 0) * 9 + p);
-          b[p] = x;
-        }
+        for (int p = 0; p < 9; ++p) b[p] = ib.ld((t * 4 + v) * 9 + p);
       };
     };
 
-    // faces: traces at the nodes, hand-over, own-trace flux, lift
-#pragma unroll
+    // faces: traces at the nodes, hand-over, own-trace flux, lift. A real
+    // loop: unrolled, the four faces' live ranges overlap and spill.
+#pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       f4 va[FT][9];
 #pragma unroll
@@ -497,8 +604,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
         for (int p = 0; p < 9; ++p) va[t][p] = f4{0.f, 0.f, 0.f, 0.f};
       const View<R, L::ldE, false> AE(lds + L::oE + f * Bf * L::ldE);
-      contract_fn<Op, View<R, L::ldE, false>, RT, FT>(va, AE, B, el, g,
-                                                      itil_at(Qg, Jg));
+      contract_fn<Op, View<R, L::ldE, false>, RT, FT, true>(va, AE, B, el, g, itil_at(Ig));
       float V[FT][4][9];
 #pragma unroll
       for (int t = 0; t < FT; ++t)
@@ -550,21 +656,10 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #endif
     }
 
-    // volume: dq += sum_d K^d (I~ (dt A*_d)^T) over the rows of I~ below B1
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const View<R, L::ldK, false> AK(lds + L::oK + d * B * L::ldK);
-      auto itil = itil_at(Qg, Jg);
-      contract_fn<Op, View<R, L::ldK, false>, RT1, RT>(dq, AK, B1, el, g, [&](int t, int v, float (&b)[9]) {
-        float x[9];
-        itil(t, v, x);
-        apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x, b);
-        if (16 * t + 4 * g + v >= B1)
-#pragma unroll
-          for (int p = 0; p < 9; ++p) b[p] = 0.0f;
-      });
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    // volume: dq += sum_d K^d (I~ (dt A*_d)^T) over the rows of I~ below B1,
+    // the three directions from one pass over I~
+    volume<Op, N>(dq, lds, itil_at(Ig), G, lam, mu, rinv, el, g);
+    __builtin_amdgcn_sched_barrier(0);
 
     {
       // Q += dq for live elements and rows below B
@@ -830,14 +925,13 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   a.gslot = d32.gslot;
   a.gD = d32.gD;
   {
-    const int RT1 = row_tiles(n_basis(M.N - 1));
-    const int64_t nJ = ((M.E + 15) >> 4) * RT1 * 36 * 64;
+    const int64_t nJ = q_size(M.E, row_tiles(n_basis(M.N)));
     void* pj = nullptr;
     hipError_t sj = hipMalloc(&pj, nJ * sizeof(float));
     if (sj != hipSuccess) return sj;
     owned.push_back(pj);
     bytes += nJ * int64_t(sizeof(float));
-    a.Jb = static_cast<float*>(pj);
+    a.Ib = static_cast<float*>(pj);
   }
   // pointwise flux coefficients: filled by the operator assembly
   float* rc[2] = {nullptr, nullptr};

@@ -24,7 +24,7 @@ struct TArgs {
   const int32_t* pinv;  // [6][Bf]
   const int32_t* gslot; // [E]
   float* gD;            // [F_g][N+1][B][9]
-  float* Jb;            // tiled [E][B1][9]: time-integral part of the derivatives, parked by the predictor
+  float* Ib;            // tiled [E][B][9]: time-integrated predictor I~ = Q + J, parked by the predictor
   const void* ref;      // reference matrices K | E | L in operand precision
   int ref_bytes;
 };
