@@ -235,6 +235,8 @@ def main():
                                f"{inf['cluster_size']}, {inf['n_gravity_faces']} gravity faces",
                    "kernel": args.kernel, "precision": args.precision, "elements": inf["n_elements"],
                    "graph": bool(args.graph), "eager_ms_per_step": eager_ms / args.steps,
+                   "launch": {"predict": inf["launch"][:3], "correct": inf["launch"][3:],
+                              "source": ["default", "measured", "cache"][inf["launch_source"]]},
                    "updates_per_step": inf["updates_per_macro_step"]},
         "roofline": roof,
         "kernels_ms": {k: v[0] for k, v in prof.items()},

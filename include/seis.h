@@ -94,7 +94,12 @@ typedef struct {
   double g;         /* gravitational acceleration (Sec. 3); default 9.81 */
   int max_clusters; /* rate-2 LTS clusters (Sec. 4.4); 1 = global time stepping */
   void *stream;     /* hipStream_t to launch on; NULL = the default stream */
-  int tile;         /* elements per work-group for the tuned kernels; 0 = autotuned default */
+  int tile;         /* elements per work-group for the tuned kernels (32: 2 wavefronts, 64: 4);
+                       0 = autotuned: at set-up the launch configurations of the matrix-core
+                       predictor and corrector are timed on the largest cluster and the fastest
+                       kept, cached per (device, order, precision, size class) in the file
+                       $SEIS_TUNE_CACHE (default $HOME/.cache/seis/tune.txt). SEIS_TUNE=0 in the
+                       environment disables tuning; SEIS_TUNE=w,cap,remap,w,cap,remap fixes it. */
   int graph;        /* nonzero: seis_step captures its macro step into a hipGraph at its first
                        call and replays that graph afterwards (one launch per macro step) */
 } seis_options_t;
@@ -114,6 +119,11 @@ typedef struct {
   int64_t cluster_size[16];
   int64_t updates_per_macro_step; /* sum_c n_c 2^(C-1-c) */
   int64_t device_bytes;
+  int launch[6];        /* matrix-core launch configuration of the predictor, then the corrector:
+                           wavefronts per work-group, work-groups per CU of a persistent grid
+                           (0 = one work-group per 16 x wavefronts elements), XCD-contiguous order */
+  int launch_source;    /* 0 default or fixed (options.tile, SEIS_TUNE), 1 measured at set-up,
+                           2 read from the tuning cache */
 } seis_info_t;
 
 /* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream,

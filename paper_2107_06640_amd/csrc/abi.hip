@@ -441,6 +441,10 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
     if (st != hipSuccess) rc = hip_fail(h, st, "tuned set-up");
   }
   if (rc == SEIS_OK) rc = assemble_ops(h);
+  if (rc == SEIS_OK && o.kernel == SEIS_KERNEL_TUNED) {
+    hipError_t st = tuned_autotune(h->tuned, h->M, h->stream);
+    if (st != hipSuccess) rc = hip_fail(h, st, "autotune");
+  }
   if (rc == SEIS_OK) {
     hipError_t st = hipDeviceSynchronize();
     if (st != hipSuccess) rc = hip_fail(h, st, "set-up sync");
@@ -686,6 +690,13 @@ int seis_info(const seis_t* h, seis_info_t* info) {
   }
   info->updates_per_macro_step = upd;
   info->device_bytes = h->buf.bytes;
+  const LaunchCfg* lc[2] = {&h->tuned.pc, &h->tuned.cc};
+  for (int k = 0; k < 2; ++k) {
+    info->launch[3 * k + 0] = lc[k]->waves;
+    info->launch[3 * k + 1] = lc[k]->cap;
+    info->launch[3 * k + 2] = lc[k]->remap;
+  }
+  info->launch_source = h->tuned.source;
   return SEIS_OK;
 }
 

@@ -23,10 +23,17 @@
 //   corrector  Q -= sum_f L_f flux(neighbour trace)
 #include <hip/hip_runtime.h>
 
+#include <sys/stat.h>
+
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <type_traits>
+#include <vector>
 
 #include "elastic.hpp"
 #include "layout.hpp"
@@ -527,8 +534,19 @@ __device__ __forceinline__ void stage_ref(void* lds, const void* ref, int bytes,
 
 // Predictor: persistent work-groups of W wavefronts; wavefront w of block b
 // handles the 16-element groups first + b*W + w, then strides by gridDim*W.
+// Logical work-group index. Work-groups are dispatched round-robin over the
+// 8 XCDs (each with its own L2); with remap, XCD x gets a contiguous range of
+// logical indices, so neighbouring 16-element groups (which exchange face
+// traces) are handled under the same L2.
+__device__ __forceinline__ int64_t logical_block(int remap) {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  if (!remap || nb < 8) return b;
+  const int64_t q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
+  return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
 template <class Op, int N, int W>
-__global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, int64_t e1, int parity) {
+__global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, int64_t e1, int parity, int remap) {
   using L = Lay<Op, N>;
   constexpr int B = L::B, Bf = L::Bf, B1 = L::B1, RT = L::RT, FT = L::FT, RT1 = L::RT1;
   using R = RefT<Op>;
@@ -541,7 +559,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int el = lane & 15, g = lane >> 4;
   const int64_t gfirst = e0 >> 4, glast = (e1 - 1) >> 4;
-  for (int64_t grp = gfirst + (int64_t)blockIdx.x * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
+  for (int64_t grp = gfirst + logical_block(remap) * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
     const int64_t e = grp * 16 + el;
     const bool live = e >= e0 && e < e1;
     const int64_t ec = live ? e : e0;
@@ -691,7 +709,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 // pass from the inbox, which is L2-resident by then) so that the accumulators
 // of one pass leave room for two wavefronts per SIMD.
 template <class Op, int N, int W>
-__global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, int64_t e1) {
+__global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, int64_t e1, int remap) {
   using L = Lay<Op, N>;
   constexpr int B = L::B, Bf = L::Bf, RT = L::RT, FT = L::FT;
   constexpr int NS = (SEIS_CORR_SPLIT > RT) ? RT : SEIS_CORR_SPLIT;
@@ -706,7 +724,7 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int el = lane & 15, g = lane >> 4;
   const int64_t gfirst = e0 >> 4, glast = (e1 - 1) >> 4;
-  for (int64_t grp = gfirst + (int64_t)blockIdx.x * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
+  for (int64_t grp = gfirst + logical_block(remap) * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
     const int64_t e = grp * 16 + el;
     const bool live = e >= e0 && e < e1;
     const int64_t ec = live ? e : e0;
@@ -782,19 +800,12 @@ int num_cus() {
   return g_num_cus;
 }
 
-// Work-groups per launch: one per group of W 16-element groups, or, when the
-// SEIS_WG_PER_CU environment variable is set to k > 0, at most k per compute
-// unit (persistent work-groups striding over the groups).
-int g_wg_per_cu = -1;
-unsigned grid_size(int64_t ngroups, int W, int lds_bytes) {
-  if (g_wg_per_cu < 0) {
-    const char* e = std::getenv("SEIS_WG_PER_CU");
-    g_wg_per_cu = e ? std::max(0, std::atoi(e)) : 0;
-  }
+// Work-groups per launch: one per W 16-element groups (cap 0), or at most cap
+// per compute unit, persistent work-groups striding over the groups.
+unsigned grid_size(int64_t ngroups, int W, int cap) {
   const int64_t full = (ngroups + W - 1) / W;
-  if (g_wg_per_cu == 0) return (unsigned)full;
-  (void)lds_bytes;
-  return (unsigned)std::min<int64_t>(full, (int64_t)num_cus() * g_wg_per_cu);
+  if (cap <= 0) return (unsigned)full;
+  return (unsigned)std::min<int64_t>(full, (int64_t)num_cus() * cap);
 }
 
 template <class KernelPtr>
@@ -803,33 +814,35 @@ hipError_t prep(KernelPtr k, int lds) {
 }
 
 template <class Op, int N, int W>
-hipError_t launch_pred(const TArgs& a, int64_t e0, int64_t e1, int parity, hipStream_t s) {
+hipError_t launch_pred(const TArgs& a, int64_t e0, int64_t e1, int parity, const LaunchCfg& c, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
   using L = Lay<Op, N>;
   const int64_t ng = ((e1 - 1) >> 4) - (e0 >> 4) + 1;
-  const unsigned grid = grid_size(ng, W, L::bytes);
+  const unsigned grid = grid_size(ng, W, c.cap);
   static hipError_t attr = prep(k_predict_tuned<Op, N, W>, L::bytes);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_predict_tuned<Op, N, W>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1, parity);
+  hipLaunchKernelGGL((k_predict_tuned<Op, N, W>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1, parity, c.remap);
   return hipGetLastError();
 }
 
 template <class Op, int N, int W>
-hipError_t launch_corr(const TArgs& a, int64_t e0, int64_t e1, hipStream_t s) {
+hipError_t launch_corr(const TArgs& a, int64_t e0, int64_t e1, const LaunchCfg& c, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
   using L = Lay<Op, N>;
   const int64_t ng = ((e1 - 1) >> 4) - (e0 >> 4) + 1;
-  const unsigned grid = grid_size(ng, W, L::bytes);
+  const unsigned grid = grid_size(ng, W, c.cap);
   static hipError_t attr = prep(k_correct_tuned<Op, N, W>, L::bytes);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_correct_tuned<Op, N, W>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1);
+  hipLaunchKernelGGL((k_correct_tuned<Op, N, W>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1, c.remap);
   return hipGetLastError();
 }
 
 template <class Op>
-hipError_t pred_dispatch(int N, int W, const TArgs& a, int64_t e0, int64_t e1, int parity, hipStream_t s) {
+hipError_t pred_dispatch(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, int parity,
+                         hipStream_t s) {
+  const int W = c.waves;
 #define SEIS_P(NN, WW) \
-  if (N == NN && W == WW) return launch_pred<Op, NN, WW>(a, e0, e1, parity, s);
+  if (N == NN && W == WW) return launch_pred<Op, NN, WW>(a, e0, e1, parity, c, s);
   SEIS_P(2, 2) SEIS_P(2, 4)
   SEIS_P(3, 2) SEIS_P(3, 4)
   SEIS_P(4, 2) SEIS_P(4, 4)
@@ -840,9 +853,10 @@ hipError_t pred_dispatch(int N, int W, const TArgs& a, int64_t e0, int64_t e1, i
 }
 
 template <class Op>
-hipError_t corr_dispatch(int N, int W, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s) {
+hipError_t corr_dispatch(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s) {
+  const int W = c.waves;
 #define SEIS_C(NN, WW) \
-  if (N == NN && W == WW) return launch_corr<Op, NN, WW>(a, e0, e1, s);
+  if (N == NN && W == WW) return launch_corr<Op, NN, WW>(a, e0, e1, c, s);
   SEIS_C(2, 2) SEIS_C(2, 4)
   SEIS_C(3, 2) SEIS_C(3, 4)
   SEIS_C(4, 2) SEIS_C(4, 4)
@@ -909,7 +923,12 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   t.d64 = d64;
   t.d32 = d32;
   t.iface_start = M.iface_start;
-  t.waves = (tile > 0 && tile <= 32) ? 2 : 4;
+  if (tile > 0) {
+    const int w = tile <= 32 ? 2 : 4;
+    t.pc = LaunchCfg{w, 0, 0};
+    t.cc = LaunchCfg{w, 0, 0};
+    t.fixed = 1;
+  }
   if (precision == 0) {  // FP64 runs the plain kernels
     t.ready = 1;
     return hipSuccess;
@@ -976,8 +995,8 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
 hipError_t tuned_predict(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
                          hipStream_t s) {
   if (precision == 0) return launch_predict_plain<double>(N, t.d64, e0, e1 - e0, parity, s);
-  hipError_t st = precision == 1 ? pred_dispatch<OpF32>(N, t.waves, t.a, e0, ei, parity, s)
-                                 : pred_dispatch<OpBF16>(N, t.waves, t.a, e0, ei, parity, s);
+  hipError_t st = precision == 1 ? pred_dispatch<OpF32>(N, t.pc, t.a, e0, ei, parity, s)
+                                 : pred_dispatch<OpBF16>(N, t.pc, t.a, e0, ei, parity, s);
   if (st != hipSuccess) return st;
   return launch_predict_plain<float>(N, t.d32, ei, e1 - ei, parity, s);
 }
@@ -985,10 +1004,172 @@ hipError_t tuned_predict(const TunedData& t, int precision, int N, int64_t e0, i
 hipError_t tuned_correct(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
                          hipStream_t s) {
   if (precision == 0) return launch_correct_plain<double>(N, t.d64, e0, e1 - e0, parity, s);
-  hipError_t st = precision == 1 ? corr_dispatch<OpF32>(N, t.waves, t.a, e0, ei, s)
-                                 : corr_dispatch<OpBF16>(N, t.waves, t.a, e0, ei, s);
+  hipError_t st = precision == 1 ? corr_dispatch<OpF32>(N, t.cc, t.a, e0, ei, s)
+                                 : corr_dispatch<OpBF16>(N, t.cc, t.a, e0, ei, s);
   if (st != hipSuccess) return st;
   return launch_correct_plain<float>(N, t.d32, ei, e1 - ei, parity, s);
+}
+
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Autotuner: candidate launch configurations are timed on the largest
+// cluster's matrix-core range; the winner is kept per (device, order,
+// precision, size class) in a text cache, one line per key:
+//   <key> <waves> <cap> <remap> <waves> <cap> <remap>   (predictor, corrector)
+// The cache is $SEIS_TUNE_CACHE, else $HOME/.cache/seis/tune.txt. SEIS_TUNE=0
+// disables tuning; SEIS_TUNE=w,cap,remap,w,cap,remap fixes the configuration.
+
+std::string cache_path() {
+  const char* e = std::getenv("SEIS_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* home = std::getenv("HOME");
+  if (!home || !*home) return "";
+  const std::string dir = std::string(home) + "/.cache/seis";
+  ::mkdir((std::string(home) + "/.cache").c_str(), 0755);
+  ::mkdir(dir.c_str(), 0755);
+  return dir + "/tune.txt";
+}
+
+std::string tune_key(const TunedData& t, int64_t ngroups) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  int lg = 0;
+  while ((int64_t(1) << (lg + 1)) <= ngroups) ++lg;
+  std::ostringstream k;
+  k << "v1/" << arch << "/cu" << num_cus() << "/N" << t.N << "/p" << t.precision << "/g" << lg;
+  return k.str();
+}
+
+bool valid(const LaunchCfg& c) { return (c.waves == 2 || c.waves == 4) && c.cap >= 0 && c.cap <= 8 && (c.remap == 0 || c.remap == 1); }
+
+bool parse_cfg(const std::string& txt, LaunchCfg& p, LaunchCfg& c) {
+  std::string t = txt;
+  std::replace(t.begin(), t.end(), ',', ' ');
+  std::istringstream in(t);
+  LaunchCfg a, b;
+  if (!(in >> a.waves >> a.cap >> a.remap >> b.waves >> b.cap >> b.remap)) return false;
+  if (!valid(a) || !valid(b)) return false;
+  p = a;
+  c = b;
+  return true;
+}
+
+// average ms of n launches of fn after one warm-up launch
+template <class F>
+hipError_t time_launch(F fn, hipStream_t s, int n, float& ms) {
+  hipEvent_t a, b;
+  hipError_t st = hipEventCreate(&a);
+  if (st != hipSuccess) return st;
+  st = hipEventCreate(&b);
+  if (st != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return st;
+  }
+  st = fn();
+  if (st == hipSuccess) st = hipEventRecord(a, s);
+  for (int i = 0; i < n && st == hipSuccess; ++i) st = fn();
+  if (st == hipSuccess) st = hipEventRecord(b, s);
+  if (st == hipSuccess) st = hipEventSynchronize(b);
+  if (st == hipSuccess) st = hipEventElapsedTime(&ms, a, b);
+  ms /= float(n);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+
+}  // namespace
+
+hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s) {
+  if (t.precision == 0 || t.fixed) return hipSuccess;
+  const char* env = std::getenv("SEIS_TUNE");
+  if (env && std::strcmp(env, "0") == 0) return hipSuccess;
+  if (env && *env && parse_cfg(env, t.pc, t.cc)) {
+    t.source = 0;
+    return hipSuccess;
+  }
+  // the largest matrix-core range of any cluster
+  int cbest = -1;
+  int64_t nbest = 0;
+  for (int c = 0; c < M.C; ++c) {
+    const int64_t n = M.iface_start[c] - M.cluster_start[c];
+    if (n > nbest) {
+      nbest = n;
+      cbest = c;
+    }
+  }
+  if (cbest < 0 || nbest < 16) return hipSuccess;
+  const int64_t e0 = M.cluster_start[cbest], ei = M.iface_start[cbest];
+  const int64_t ngroups = ((ei - 1) >> 4) - (e0 >> 4) + 1;
+  const std::string key = tune_key(t, ngroups);
+  const std::string path = cache_path();
+  if (!path.empty()) {
+    std::ifstream in(path);
+    std::string line;
+    LaunchCfg p, c;
+    bool hit = false;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      if (!(ls >> k) || k != key) continue;
+      std::string rest;
+      std::getline(ls, rest);
+      if (parse_cfg(rest, p, c)) hit = true;
+    }
+    if (hit) {
+      t.pc = p;
+      t.cc = c;
+      t.source = 2;
+      return hipSuccess;
+    }
+  }
+  const int reps = 2;
+  LaunchCfg bp = t.pc, bc = t.cc;
+  float tp = 1e30f, tc = 1e30f;
+  for (int w : {4, 2})
+    for (int cap : {0, 1, 2, 4})
+      for (int rm : {0, 1}) {
+        const LaunchCfg c{w, cap, rm};
+        float ms = 0.0f;
+        if (cap <= 2) {
+          hipError_t st = time_launch(
+              [&]() {
+                return t.precision == 1 ? pred_dispatch<OpF32>(t.N, c, t.a, e0, ei, 0, s)
+                                        : pred_dispatch<OpBF16>(t.N, c, t.a, e0, ei, 0, s);
+              },
+              s, reps, ms);
+          if (st != hipSuccess) return st;
+          if (ms < tp) {
+            tp = ms;
+            bp = c;
+          }
+        }
+        hipError_t st = time_launch(
+            [&]() {
+              return t.precision == 1 ? corr_dispatch<OpF32>(t.N, c, t.a, e0, ei, s)
+                                      : corr_dispatch<OpBF16>(t.N, c, t.a, e0, ei, s);
+            },
+            s, reps, ms);
+        if (st != hipSuccess) return st;
+        if (ms < tc) {
+          tc = ms;
+          bc = c;
+        }
+      }
+  t.pc = bp;
+  t.cc = bc;
+  t.source = 1;
+  if (!path.empty()) {
+    std::ofstream out(path, std::ios::app);
+    if (out) out << key << ' ' << bp.waves << ' ' << bp.cap << ' ' << bp.remap << ' ' << bc.waves << ' ' << bc.cap
+                 << ' ' << bc.remap << '\n';
+  }
+  return hipSuccess;
 }
 
 }  // namespace seis

@@ -29,11 +29,20 @@ struct TArgs {
   int ref_bytes;
 };
 
+// Launch configuration of one tuned kernel.
+struct LaunchCfg {
+  int waves = 4;  // wavefronts per work-group (16 elements each): 2 or 4
+  int cap = 0;    // work-groups per compute unit of a persistent grid; 0 = one work-group per 16*waves elements
+  int remap = 0;  // 1: XCD-contiguous work-group order
+};
+
 struct TunedData {
   int ready = 0;
   int N = 0;
   int precision = 0;
-  int waves = 4;   // wavefronts per work-group (16 elements each)
+  LaunchCfg pc{}, cc{};  // predictor, corrector
+  int fixed = 0;         // configuration fixed by the caller (options.tile)
+  int source = 0;        // 0 default or fixed, 1 measured at set-up, 2 read from the tuning cache
   TArgs a{};
   std::vector<int64_t> iface_start;   // per cluster: first element handled by the plain kernels
   DevData<double> d64{};
@@ -48,5 +57,9 @@ hipError_t tuned_predict(const TunedData& t, int precision, int N, int64_t e0, i
                          hipStream_t s);
 hipError_t tuned_correct(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
                          hipStream_t s);
+// Choose pc and cc for the largest cluster's matrix-core range [e0, ei) by
+// timing the candidates on the (zero) state left by set-up, or read them from
+// the tuning cache. The state stays zero: every kernel is linear.
+hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s);
 
 }  // namespace seis

@@ -1,0 +1,65 @@
+"""Autotuned launch configurations of the matrix-core kernels.
+
+The tuner times predictor and corrector launch configurations (wavefronts per
+work-group, persistent-grid size, XCD-contiguous order) at set-up and keeps
+the fastest in a cache file. Every configuration computes each 16-element
+group the same way, so results must agree bit for bit across configurations.
+"""
+import numpy as np
+import pytest
+
+from paper_2107_06640_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def box():
+    return inputs.coupled_box(6, 6, 4, cell=500.0, water_layers=1, jitter=0.1, seed=7)
+
+
+def run(mesh, mats, precision, steps=2):
+    from paper_2107_06640_amd import seis
+    s = seis.from_mesh(mesh, mats, 6, precision=precision, kernel="tuned")
+    try:
+        q = inputs.random_dofs(mesh.n_elements, s.B, seed=3, acoustic=mats[2] == 0)
+        s.write(q)
+        s.run(steps)
+        return s.read()[0], s.info()
+    finally:
+        s.close()
+
+
+def test_autotune_measures_then_reads_cache(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("SEIS_TUNE_CACHE", str(cache))
+    monkeypatch.delenv("SEIS_TUNE", raising=False)
+    mesh, mats = box()
+    _, i1 = run(mesh, mats, "fp32", steps=0)
+    assert i1["launch_source"] == 1
+    w, cap, rm = i1["launch"][:3]
+    assert w in (2, 4) and 0 <= cap <= 8 and rm in (0, 1)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and "/N5/p1/" in lines[0]
+    _, i2 = run(mesh, mats, "fp32", steps=0)
+    assert i2["launch_source"] == 2 and i2["launch"] == i1["launch"]
+    _, i3 = run(mesh, mats, "bf16", steps=0)   # another key: measured again
+    assert i3["launch_source"] == 1
+    assert len(cache.read_text().splitlines()) == 2
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_launch_configurations_agree_bitwise(tmp_path, monkeypatch, precision):
+    mesh, mats = box()
+    monkeypatch.setenv("SEIS_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    outs = []
+    for cfg in ("4,0,0,4,0,0", "2,1,1,2,2,1", "4,2,1,2,4,0", None):
+        if cfg is None:
+            monkeypatch.delenv("SEIS_TUNE", raising=False)
+        else:
+            monkeypatch.setenv("SEIS_TUNE", cfg)
+        d, inf = run(mesh, mats, precision)
+        if cfg is not None:
+            assert inf["launch"] == [int(x) for x in cfg.split(",")] and inf["launch_source"] == 0
+        outs.append(d)
+    for d in outs[1:]:
+        assert np.array_equal(d, outs[0])
