@@ -85,6 +85,62 @@ def tiled_dofs(E, B, seed, wet):
     return q
 
 
+def precision_sweep(args):
+    """Per-field error of FP32 and BF16 against FP64, and throughput, at orders 4-7.
+
+    The benchmark mesh, 504 sub-steps of dt_min (63 macro steps of 8), from
+    seeded Gaussian v_z pulses at the seafloor. The FP64 reference is the
+    library's FP64 path (plain kernels), the one the parity tests pin to the
+    oracle. Prints one JSON line per (order, precision).
+    """
+    import torch
+    from paper_2107_06640_amd import inputs, seis
+    mesh, mats = workload(args.scale)
+    X = mesh.xyz[mesh.tet]
+    J = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+    w = np.abs(np.linalg.det(J))
+    del X, J
+    z_floor = mesh.info["z_seafloor"]
+    macro = args.sweep_steps
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    def run(order, precision, kernel, q):
+        s = seis.from_mesh(mesh, mats, order, precision=precision, kernel=kernel, max_clusters=args.max_clusters,
+                           stream=stream.cuda_stream)
+        inf = s.info()
+        s.write(q)
+        s.sync()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        s.run(macro)
+        b.record(stream)
+        b.synchronize()
+        d, e = s.read()
+        s.close()
+        sub = macro * (1 << (inf["n_clusters"] - 1))
+        return d, e, inf["updates_per_macro_step"] * macro / (a.elapsed_time(b) / 1e3), sub
+
+    for order in args.sweep_orders:
+        B = (order) * (order + 1) * (order + 2) // 6
+        q = inputs.pulse_dofs(mesh, B, z_floor, 500.0, seed=0)
+        ref, ref_eta, ups, sub = run(order, "fp64", "plain", q)
+        nrm = np.sqrt(np.einsum("e,ebp->p", w, ref ** 2))
+        print(json.dumps({"order": order, "precision": "fp64", "kernel": "plain", "substeps": sub,
+                          "updates_per_s": ups}), flush=True)
+        for prec in ("fp32", "bf16"):
+            d, eta, ups, _ = run(order, prec, "tuned", q)
+            err = np.sqrt(np.einsum("e,ebp->p", w, (d - ref) ** 2))
+            rel = err / np.where(nrm > 0, nrm, nrm.max())
+            ee = float(np.linalg.norm(eta - ref_eta) / max(np.linalg.norm(ref_eta), 1e-300))
+            print(json.dumps({"order": order, "precision": prec, "kernel": "tuned", "substeps": sub,
+                              "updates_per_s": ups, "rel_l2_per_field": [float(x) for x in rel],
+                              "rel_l2_eta": ee}), flush=True)
+            del d
+        del ref
+
+
 def cpu_baseline(order, budget_s=15.0):
     """Oracle element-updates/s on a 6 x 6 x 8-cube sample of the workload (GTS)."""
     from oracle.solver import Oracle
@@ -127,6 +183,10 @@ def main():
                     help="replay each macro step as one hipGraph; kernel timings then come from a "
                          "separate eagerly launched pass of the same length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="precision sweep: FP32/BF16 against FP64 at orders 4-7 (one JSON line each)")
+    ap.add_argument("--sweep-orders", type=int, nargs="+", default=[4, 5, 6, 7])
+    ap.add_argument("--sweep-steps", type=int, default=63, help="macro steps (63 x 8 = 504 sub-steps)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
@@ -141,6 +201,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 3}),
               flush=True)
+        return
+
+    if args.sweep:
+        precision_sweep(args)
         return
 
     if args.gpus != 1:

@@ -223,6 +223,33 @@ def random_dofs(n_elements: int, n_basis: int, seed: int = 0, *, stress_scale=1.
     return q
 
 
+def pulse_dofs(mesh: Mesh, n_basis: int, z_center: float, cell: float, seed: int = 0,
+               n_pulses: int = 3) -> np.ndarray:
+    """Seeded sum of Gaussian v_z pulses centred at depth ``z_center``, one value per element.
+
+    Widths 2-5 cells, amplitudes U[0.5, 1.5] m/s, centres at least two widths
+    from the lateral edges. The pulse is sampled at each element's centroid
+    and carried by the constant basis function only (its value on the unit-
+    norm reference basis is sqrt(6), the reference volume being 1/6), so the
+    initial state is piecewise constant.
+    """
+    rng = np.random.default_rng(seed)
+    c = centroids(mesh)
+    lo, hi = mesh.xyz.min(axis=0), mesh.xyz.max(axis=0)
+    v = np.zeros(mesh.n_elements)
+    for _ in range(n_pulses):
+        w = rng.uniform(2.0, 5.0) * cell
+        a = rng.uniform(0.5, 1.5)
+        m = np.minimum(2 * w, 0.45 * (hi[:2] - lo[:2]))
+        cx = rng.uniform(lo[0] + m[0], hi[0] - m[0])
+        cy = rng.uniform(lo[1] + m[1], hi[1] - m[1])
+        r2 = (c[:, 0] - cx) ** 2 + (c[:, 1] - cy) ** 2 + (c[:, 2] - z_center) ** 2
+        v += a * np.exp(-r2 / (2 * w * w))
+    q = np.zeros((mesh.n_elements, n_basis, 9))
+    q[:, 0, 8] = v / np.sqrt(6.0)
+    return q
+
+
 # ---------------------------------------------------------------------------
 # Workload builders. Sizes are those of the benchmark configurations; the
 # functions take a ``scale`` to build smaller meshes of the same shape.
