@@ -1,0 +1,96 @@
+"""CPU checks of the surrogate: oracle pins, and the driver's composition of
+products (through CPU stand-in kernels) against the oracle.
+
+Pins of the oracle (independent of its own code path):
+* a single real Fourier mode through a spectral layer whose mixing matrix is
+  c times the identity comes out as Re(c) cos(theta) - Im(c) sin(theta)
+  (closed form), and a mode outside the kept set comes out as zero;
+* gradients from automatic differentiation match central finite differences;
+* one Adam step from zero moments moves each parameter by lr sign(g) (up to
+  eps), the closed form of the first bias-corrected step.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fno as ofno
+from tests.fno_reference_kernels import ReferenceKernels
+
+
+def small_params(rng, cin, W, m, L, H):
+    nm = (2 * m) ** 2 * m
+    p = {"P": rng.standard_normal((W, cin)) * 0.5, "p": rng.standard_normal(W) * 0.1}
+    for l in range(L):
+        p[f"W{l}"] = rng.standard_normal((W, W)) * 0.4
+        p[f"b{l}"] = rng.standard_normal(W) * 0.1
+        p[f"R{l}"] = rng.standard_normal((2, nm, W, W)) * 0.3
+    p["Q1"] = rng.standard_normal((H, W)) * 0.4
+    p["q1"] = rng.standard_normal(H) * 0.1
+    p["Q2"] = rng.standard_normal((1, H)) * 0.4
+    p["q2"] = rng.standard_normal(1) * 0.1
+    return p
+
+
+def test_single_mode_through_spectral_layer():
+    X, Y, T, m = 8, 8, 8, 3
+    x, y, t = np.meshgrid(np.arange(X), np.arange(Y), np.arange(T), indexing="ij")
+    c = 0.7 - 0.4j
+    nm = (2 * m) ** 2 * m
+    R = np.zeros((2, nm, 1, 1))
+    R[0, :, 0, 0], R[1, :, 0, 0] = c.real, c.imag
+    for (kx, ky, kt), kept in (((1, 7, 2), True), ((2, 1, 1), True), ((3, 0, 1), False), ((1, 1, 3), False)):
+        th = 2 * np.pi * (kx * x / X + ky * y / Y + kt * t / T)
+        v = torch.tensor(np.cos(th)[None, None])
+        out = ofno.spectral(v, torch.tensor(R), m).numpy()[0, 0]
+        want = (c.real * np.cos(th) - c.imag * np.sin(th)) if kept else np.zeros_like(th)
+        assert np.abs(out - want).max() < 1e-12, (kx, ky, kt)
+
+
+def test_oracle_gradients_match_finite_differences():
+    rng = np.random.default_rng(1)
+    cin, W, m, L, H, X, Y, T, B = 2, 3, 2, 2, 4, 6, 6, 4, 2
+    p = small_params(rng, cin, W, m, L, H)
+    u = rng.standard_normal((cin, B, X, Y, T))
+    y = rng.standard_normal((1, B, X, Y, T))
+    loss, _, g = ofno.loss_and_grads(p, u, y, m, L)
+    h = 1e-6
+    for name in ("P", "W1", "R0", "Q1", "q2", "b0"):
+        flat = p[name].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(4, flat.size), replace=False):
+            q = {k: v.copy() for k, v in p.items()}
+            q[name].reshape(-1)[idx] += h
+            lp = ofno.loss_and_grads(q, u, y, m, L)[0]
+            q[name].reshape(-1)[idx] -= 2 * h
+            lm = ofno.loss_and_grads(q, u, y, m, L)[0]
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name].reshape(-1)[idx]) < 1e-6 * max(1.0, abs(fd)), (name, idx)
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    g = np.array([3.0, -0.2, 1e-3, -50.0])
+    p, m, v = ofno.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 0.01, 0.9, 0.999, 1e-12, 1)
+    assert np.allclose(p, -0.01 * np.sign(g), rtol=1e-8, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8, 2, 3), (12, 8, 6, 3, 2)])
+def test_driver_composition_matches_oracle(shape):
+    from paper_2107_06640_amd.fno import FNO
+    X, Y, T, m, B = shape
+    cin, W, L, H = 3, 4, 2, 5
+    net = FNO(X, Y, T, cin=cin, width=W, modes=m, layers=L, hidden=H, device="cpu", kernels=ReferenceKernels(),
+              dtype=torch.float64)
+    rng = np.random.default_rng(2)
+    p = small_params(rng, cin, W, m, L, H)
+    net.load_numpy_params(p)
+    u = rng.standard_normal((cin, B, X, Y, T))
+    yt = rng.standard_normal((1, B, X, Y, T))
+    ut = torch.tensor(u)
+    yhat = net.forward(ut, keep=True)
+    loss, grad = net.loss(yhat, torch.tensor(yt))
+    net.backward(grad)
+    ref_loss, ref_y, ref_g = ofno.loss_and_grads(p, u, yt, m, L)
+    assert np.abs(yhat.numpy() - ref_y).max() < 1e-10 * np.abs(ref_y).max()
+    assert abs(float(loss[0]) - ref_loss) < 1e-12
+    for k, v in ref_g.items():
+        got = net.grads[k].numpy()
+        assert np.abs(got - v).max() <= 1e-9 * max(np.abs(v).max(), 1e-12), k
