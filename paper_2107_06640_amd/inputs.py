@@ -250,6 +250,43 @@ def pulse_dofs(mesh: Mesh, n_basis: int, z_center: float, cell: float, seed: int
     return q
 
 
+def uplift_sources(seed: int, lx: float, ly: float, n_min: int = 1, n_max: int = 4):
+    """Seeded seafloor uplift: 1-4 Gaussians (amplitude 0.5-3 m, width 2-6 km, rise time 5-30 s).
+
+    Returns a list of (amplitude, x, y, width, rise time); centres keep one
+    width from the lateral edges when the box allows it.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(int(rng.integers(n_min, n_max + 1))):
+        a = rng.uniform(0.5, 3.0)
+        w = rng.uniform(2000.0, 6000.0)
+        mx, my = min(w, 0.45 * lx), min(w, 0.45 * ly)
+        out.append((a, rng.uniform(mx, lx - mx), rng.uniform(my, ly - my), w, rng.uniform(5.0, 30.0)))
+    return out
+
+
+def uplift_rate(x, y, sources):
+    """Mean uplift rate sum_j A_j/T_j exp(-r_j^2 / (2 w_j^2)) at points (x, y), m/s."""
+    v = np.zeros(np.broadcast(x, y).shape)
+    for a, cx, cy, w, tr in sources:
+        v = v + (a / tr) * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2 * w * w))
+    return v
+
+
+def uplift_dofs(mesh: Mesh, n_basis: int, z_floor: float, sources, thickness: float, elastic) -> np.ndarray:
+    """Initial v_z of the rock under the seafloor: the uplift rate times exp(-(z - z_floor)^2 / (2 h^2)).
+
+    Piecewise constant (constant basis function only, value sqrt(6) on the
+    unit-norm reference basis); zero in the water.
+    """
+    c = centroids(mesh)
+    v = uplift_rate(c[:, 0], c[:, 1], sources) * np.exp(-((c[:, 2] - z_floor) ** 2) / (2 * thickness ** 2))
+    q = np.zeros((mesh.n_elements, n_basis, 9))
+    q[:, 0, 8] = np.where(np.asarray(elastic, bool), v, 0.0) / np.sqrt(6.0)
+    return q
+
+
 # ---------------------------------------------------------------------------
 # Workload builders. Sizes are those of the benchmark configurations; the
 # functions take a ``scale`` to build smaller meshes of the same shape.
@@ -280,6 +317,14 @@ def cfg2(scale: int = 1, seed: int = 0):
     nx, ny, nz = 40 // scale, 40 // scale, 20 // scale
     m, mat = coupled_box(nx, ny, nz, cell=500.0, water_layers=max(1, nz // 4), seed=seed)
     m.info.update(name="cfg2-coupled-gravity")
+    return m, mat
+
+
+def cfg5(scale: int = 1, seed: int = 0):
+    """24x24x12 cubes of 1 km x 6 tets (41 472 elements), top 3 layers water (surrogate data)."""
+    nx, ny, nz = 24 // scale, 24 // scale, 12 // scale
+    m, mat = coupled_box(nx, ny, nz, cell=1000.0, water_layers=max(1, nz // 4), seed=seed)
+    m.info.update(name="cfg5-surrogate")
     return m, mat
 
 
