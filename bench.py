@@ -48,8 +48,14 @@ def nf(N):
 def algorithmic_counts(N, value_bytes):
     """Per-element algorithmic flops and HBM bytes of the predictor and corrector kernels.
 
-    Star matrices count with their 24 non-zeros, flux matrices dense 9x9,
-    face traces at Bf nodes per face.
+    Flops: CK with shrinking support (star matrices at 24 non-zeros), the time
+    integral, the volume term over the B_{N-1} non-zero columns of K^d, face
+    traces and lifts at B_f nodes (2 B_f B 9 each per face) and the pointwise
+    Riemann solve (9 x 9 per node). Bytes: what the executed form must move
+    at least once: the predictor reads Q, G (9), material (3) and the own-trace
+    flux coefficients (4 x 12) and writes Q and the 4 B_f x 9 traces it hands
+    over; the corrector reads its 4 B_f x 9 inbox, material, the neighbour-
+    trace coefficients (4 x 12) and reads and writes Q.
     """
     B, Bf, B1 = nb(N), nf(N), nb(N - 1)
     ck = sum(2 * 3 * nb(N - k - 1) * nb(N - k) * 9 + 2 * nb(N - k - 1) * 72 for k in range(N))
@@ -61,8 +67,8 @@ def algorithmic_counts(N, value_bytes):
     pred_flops = ck + tint + traces + flux + volume + lift
     corr_flops = flux + lift
     vb = value_bytes
-    pred_bytes = vb * (B * 9 + 12 + 4 * 81 + 4 * Bf * 9 + B * 9)
-    corr_bytes = vb * (B * 9 + 4 * Bf * 9 + 4 * 81 + B * 9)
+    pred_bytes = vb * (B * 9 + 12 + 4 * 12 + 4 * Bf * 9 + B * 9)
+    corr_bytes = vb * (4 * Bf * 9 + 3 + 4 * 12 + 2 * B * 9)
     return dict(pred_flops=pred_flops, corr_flops=corr_flops, pred_bytes=pred_bytes, corr_bytes=corr_bytes)
 
 
