@@ -198,6 +198,13 @@ struct View {
 template <class Op, class V>
 __device__ __forceinline__ void mma_slice(f4& acc, const V& A, int i, int k, float b);
 
+#ifndef SEIS_PREFETCH
+#define SEIS_PREFETCH 2  // rows requested ahead by the pipelined contractions
+#endif
+#ifndef SEIS_NT_STORE
+#define SEIS_NT_STORE 0
+#endif
+
 // acc[mt][p] += sum_k A(16 mt + el, k) X[k][p]; X rows produced by rowfn(t, v, b[9])
 // for the input rows k < nrows (rows 16t + 4g + v of this lane). With PIPE the
 // rows come from memory: the next row (FP32) or row tile (BF16) is requested
@@ -207,16 +214,19 @@ __device__ __forceinline__ void mma_slice(f4& acc, const V& A, int i, int k, flo
 template <class Op, class V, int NT, int MT, bool PIPE = false, class RowFn>
 __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nrows, int el, int g, RowFn rowfn) {
   if constexpr (std::is_same<Op, OpF32>::value) {
-    float b[2][9];
-    if constexpr (PIPE) rowfn(0, 0, b[0]);
+    constexpr int D = PIPE ? SEIS_PREFETCH : 0;  // rows requested ahead
+    float b[D + 1][9];
+    auto valid = [&](int i) { return i < 4 * NT && 16 * (i >> 2) + (i & 3) < nrows; };
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (valid(j)) rowfn(j >> 2, j & 3, b[j % (D + 1)]);
 #pragma unroll
     for (int i = 0; i < 4 * NT; ++i) {
       const int t = i >> 2, v = i & 3;
-      if (16 * t + v >= nrows) continue;
-      float(&cur)[9] = b[i & 1];
+      if (!valid(i)) continue;
+      float(&cur)[9] = b[i % (D + 1)];
       if constexpr (PIPE) {
-        const int tn = (i + 1) >> 2, vn = (i + 1) & 3;
-        if (i + 1 < 4 * NT && 16 * tn + vn < nrows) rowfn(tn, vn, b[(i + 1) & 1]);
+        if (valid(i + D)) rowfn((i + D) >> 2, (i + D) & 3, b[(i + D) % (D + 1)]);
       } else {
         rowfn(t, v, cur);
       }
@@ -457,15 +467,18 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
   using R = RefT<Op>;
   const View<R, L::ldK, false> A0(lds + L::oK), A1(lds + L::oK + B * L::ldK), A2(lds + L::oK + 2 * B * L::ldK);
   if constexpr (std::is_same<Op, OpF32>::value) {
-    float xb[2][9];
-    rowfn(0, 0, xb[0]);
+    constexpr int D = SEIS_PREFETCH;
+    float xb[D + 1][9];
+    auto valid = [&](int i) { return i < 4 * RT1 && 16 * (i >> 2) + (i & 3) < B1; };
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (valid(j)) rowfn(j >> 2, j & 3, xb[j % (D + 1)]);
 #pragma unroll
     for (int i = 0; i < 4 * RT1; ++i) {
       const int t = i >> 2, v = i & 3;
-      if (16 * t + v >= B1) continue;
-      const int tn = (i + 1) >> 2, vn = (i + 1) & 3;
-      if (i + 1 < 4 * RT1 && 16 * tn + vn < B1) rowfn(tn, vn, xb[(i + 1) & 1]);
-      const float(&x)[9] = xb[i & 1];
+      if (!valid(i)) continue;
+      if (valid(i + D)) rowfn((i + D) >> 2, (i + D) & 3, xb[(i + D) % (D + 1)]);
+      const float(&x)[9] = xb[i % (D + 1)];
       const bool ok = 16 * t + 4 * g + v < B1;
       float z[3][9];
 #pragma unroll
@@ -646,7 +659,11 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
             for (int p = 0; p < 9; ++p) {
               float* dst = a.In + inidx(tg >> 2, tg & 3, mr, p, FT);
+#if SEIS_NT_STORE
+              if (md == 1) __builtin_nontemporal_store(V[t][v][p], dst);
+#else
               if (md == 1) *dst = V[t][v][p];
+#endif
               else *dst = parity ? *dst + 0.5f * V[t][v][p] : 0.5f * V[t][v][p];
             }
           }
