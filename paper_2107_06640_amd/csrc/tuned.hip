@@ -380,10 +380,10 @@ __device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const bool ok = 16 * t + 4 * g + v < B;
+      // rows >= B are the zero padding of the tiled layout: loaded as they are,
+      // so that no load sits behind a lane-dependent branch
 #pragma unroll
-      for (int p = 0; p < 9; ++p)
-        din[t][v][p] = (p >= C0 && p < C1) ? (ok ? qb.ld((t * 4 + v) * 9 + p) : 0.0f) : 0.0f;
+      for (int p = 0; p < 9; ++p) din[t][v][p] = (p >= C0 && p < C1) ? qb.ld((t * 4 + v) * 9 + p) : 0.0f;
     }
   if (gd) {
 #pragma unroll
@@ -572,6 +572,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int el = lane & 15, g = lane >> 4;
   const int64_t gfirst = e0 >> 4, glast = (e1 - 1) >> 4;
+  (void)parity;  // every face here hands over a full-step trace
   for (int64_t grp = gfirst + logical_block(remap) * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
     const int64_t e = grp * 16 + el;
     const bool live = e >= e0 && e < e1;
@@ -581,7 +582,8 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     for (int i = 0; i < 9; ++i) G[i] = a.G[ec * 9 + i];
     const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
     const float* Qg = a.Q + grp * (int64_t)(RT * 36 * 64);
-    const int gs = live ? a.gslot[e] : -1;
+    const int gs0 = a.gslot[ec];
+    const int gs = live ? gs0 : -1;
     float* gd = gs >= 0 ? a.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
 
     // I~ = Q + J (J = sum_{k>=1} Dk/(k+1)) is parked in memory in the same
@@ -592,20 +594,23 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     {
       float J[RT1][4][9];
       CK<Op, N>::run(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
+      // a row tile of Q is loaded before any of its stores: raw buffer
+      // accesses may alias, so a store between two loads would serialise them
       const GroupBuf qb(Qg, RT * 36 * 256, lane), ib(Ig, RT * 36 * 256, lane);
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
+      for (int t = 0; t < RT; ++t) {
+        float x[36];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const bool ok = 16 * t + 4 * g + v < B;
+        for (int r = 0; r < 36; ++r) x[r] = qb.ld(t * 36 + r);  // zero on the padding rows
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
           for (int p = 0; p < 9; ++p) {
-            const int r = (t * 4 + v) * 9 + p;
-            float x = ok ? qb.ld(r) : 0.0f;
-            if (t < RT1) x += J[t < RT1 ? t : 0][v][p];
-            ib.st(r, x);
+            float y = x[v * 9 + p];
+            if (t < RT1) y += J[t < RT1 ? t : 0][v][p];
+            ib.st((t * 4 + v) * 9 + p, y);
           }
-        }
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -645,26 +650,31 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
           for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? va[t][p][v] : 0.0f;
         }
-      const int md = live ? a.mode[ec * 4 + f] : 0;
-      if (md != 0) {
-        const int32_t tg = a.tgt[ec * 4 + f];
+      // hand-over: these elements have all face neighbours in their own
+      // cluster (the others run on the plain kernels), so every paired face
+      // receives the full-step trace. Loads are unconditional (valid indices
+      // for every lane); only the stores are masked.
+      {
+        const int md0 = a.mode[ec * 4 + f];
+        const int32_t tg0 = a.tgt[ec * 4 + f];
         const int h = a.hperm[ec * 4 + f];
+        const bool send = live && md0 != 0;
+        const int32_t tg = send ? tg0 : 0;
 #pragma unroll
         for (int t = 0; t < FT; ++t)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int node = 16 * t + 4 * g + v;
-            if (node >= Bf) continue;
-            const int mr = a.pinv[h * Bf + node];
+            const int mr = a.pinv[h * Bf + (node < Bf ? node : Bf - 1)];
+            if (!send || node >= Bf) continue;
 #pragma unroll
             for (int p = 0; p < 9; ++p) {
               float* dst = a.In + inidx(tg >> 2, tg & 3, mr, p, FT);
 #if SEIS_NT_STORE
-              if (md == 1) __builtin_nontemporal_store(V[t][v][p], dst);
+              __builtin_nontemporal_store(V[t][v][p], dst);
 #else
-              if (md == 1) *dst = V[t][v][p];
+              *dst = V[t][v][p];
 #endif
-              else *dst = parity ? *dst + 0.5f * V[t][v][p] : 0.5f * V[t][v][p];
             }
           }
       }
@@ -700,16 +710,17 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
       // Q += dq for live elements and rows below B
       const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
+      for (int t = 0; t < RT; ++t) {
+        float q[36];  // the whole row tile before its stores (see the park above)
+#pragma unroll
+        for (int r = 0; r < 36; ++r) q[r] = qb.ld(t * 36 + r);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           if (!live || 16 * t + 4 * g + v >= B) continue;
 #pragma unroll
-          for (int p = 0; p < 9; ++p) {
-            const int r = (t * 4 + v) * 9 + p;
-            qb.st(r, qb.ld(r) + dq[t][p][v]);
-          }
+          for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[v * 9 + p] + dq[t][p][v]);
         }
+      }
     }
   }
 }
@@ -790,14 +801,14 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
       for (int tt = 0; tt < MH; ++tt) {
         const int t = t0 + tt;
         if (t >= RT) continue;
+        float q[36];  // the whole row tile before its stores (raw buffer accesses may alias)
+#pragma unroll
+        for (int r = 0; r < 36; ++r) q[r] = qb.ld(t * 36 + r);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           if (!live || 16 * t + 4 * g + v >= B) continue;
 #pragma unroll
-          for (int p = 0; p < 9; ++p) {
-            const int r = (t * 4 + v) * 9 + p;
-            qb.st(r, qb.ld(r) + dq[tt][p][v]);
-          }
+          for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[v * 9 + p] + dq[tt][p][v]);
         }
       }
     }
