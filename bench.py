@@ -335,7 +335,7 @@ def main():
                                f"{inf['cluster_size']}, {inf['n_gravity_faces']} gravity faces",
                    "kernel": args.kernel, "precision": args.precision, "elements": inf["n_elements"],
                    "graph": bool(args.graph), "eager_ms_per_step": eager_ms / args.steps,
-                   "launch": {"predict": inf["launch"][:3], "correct": inf["launch"][3:],
+                   "launch": {"predict": inf["launch"][:3], "correct": inf["launch"][3:7],
                               "source": ["default", "measured", "cache"][inf["launch_source"]]},
                    "updates_per_step": inf["updates_per_macro_step"]},
         "roofline": roof,

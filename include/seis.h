@@ -99,7 +99,8 @@ typedef struct {
                        predictor and corrector are timed on the largest cluster and the fastest
                        kept, cached per (device, order, precision, size class) in the file
                        $SEIS_TUNE_CACHE (default $HOME/.cache/seis/tune.txt). SEIS_TUNE=0 in the
-                       environment disables tuning; SEIS_TUNE=w,cap,remap,w,cap,remap fixes it. */
+                       environment disables tuning; SEIS_TUNE=w,cap,remap,w,cap,remap[,split]
+                       fixes it. */
   int graph;        /* nonzero: seis_step captures its macro step into a hipGraph at its first
                        call and replays that graph afterwards (one launch per macro step) */
 } seis_options_t;
@@ -119,9 +120,10 @@ typedef struct {
   int64_t cluster_size[16];
   int64_t updates_per_macro_step; /* sum_c n_c 2^(C-1-c) */
   int64_t device_bytes;
-  int launch[6];        /* matrix-core launch configuration of the predictor, then the corrector:
+  int launch[8];        /* matrix-core launch configuration of the predictor, then the corrector:
                            wavefronts per work-group, work-groups per CU of a persistent grid
-                           (0 = one work-group per 16 x wavefronts elements), XCD-contiguous order */
+                           (0 = one work-group per 16 x wavefronts elements), XCD-contiguous order;
+                           [6] the corrector's passes over its output rows; [7] unused (0) */
   int launch_source;    /* 0 default or fixed (options.tile, SEIS_TUNE), 1 measured at set-up,
                            2 read from the tuning cache */
 } seis_info_t;

@@ -696,6 +696,8 @@ int seis_info(const seis_t* h, seis_info_t* info) {
     info->launch[3 * k + 1] = lc[k]->cap;
     info->launch[3 * k + 2] = lc[k]->remap;
   }
+  info->launch[6] = h->tuned.cc.split;
+  info->launch[7] = 0;
   info->launch_source = h->tuned.source;
   return SEIS_OK;
 }

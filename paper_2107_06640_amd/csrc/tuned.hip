@@ -725,22 +725,19 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
   }
 }
 
-#ifndef SEIS_CORR_SPLIT
-#define SEIS_CORR_SPLIT 2
-#endif
 #ifndef SEIS_FACE_BARRIER
 #define SEIS_FACE_BARRIER 1
 #endif
 
 // Corrector: Q -= sum_f L_f flux(neighbour trace of face f). The output rows
-// are produced in SEIS_CORR_SPLIT passes (the face fluxes are recomputed per
+// are produced in SPLIT passes (the face fluxes are recomputed per
 // pass from the inbox, which is L2-resident by then) so that the accumulators
 // of one pass leave room for two wavefronts per SIMD.
-template <class Op, int N, int W>
+template <class Op, int N, int W, int SPLIT>
 __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, int64_t e1, int remap) {
   using L = Lay<Op, N>;
   constexpr int B = L::B, Bf = L::Bf, RT = L::RT, FT = L::FT;
-  constexpr int NS = (SEIS_CORR_SPLIT > RT) ? RT : SEIS_CORR_SPLIT;
+  constexpr int NS = (SPLIT > RT) ? RT : SPLIT;
   constexpr int MH = (RT + NS - 1) / NS;  // row tiles per pass
   using R = RefT<Op>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -853,15 +850,15 @@ hipError_t launch_pred(const TArgs& a, int64_t e0, int64_t e1, int parity, const
   return hipGetLastError();
 }
 
-template <class Op, int N, int W>
+template <class Op, int N, int W, int SPLIT>
 hipError_t launch_corr(const TArgs& a, int64_t e0, int64_t e1, const LaunchCfg& c, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
   using L = Lay<Op, N>;
   const int64_t ng = ((e1 - 1) >> 4) - (e0 >> 4) + 1;
   const unsigned grid = grid_size(ng, W, c.cap);
-  static hipError_t attr = prep(k_correct_tuned<Op, N, W>, L::bytes);
+  static hipError_t attr = prep(k_correct_tuned<Op, N, W, SPLIT>, L::bytes);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_correct_tuned<Op, N, W>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1, c.remap);
+  hipLaunchKernelGGL((k_correct_tuned<Op, N, W, SPLIT>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1, c.remap);
   return hipGetLastError();
 }
 
@@ -883,8 +880,9 @@ hipError_t pred_dispatch(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, 
 template <class Op>
 hipError_t corr_dispatch(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s) {
   const int W = c.waves;
-#define SEIS_C(NN, WW) \
-  if (N == NN && W == WW) return launch_corr<Op, NN, WW>(a, e0, e1, c, s);
+#define SEIS_C(NN, WW)                                                                   \
+  if (N == NN && W == WW)                                                                \
+    return c.split == 1 ? launch_corr<Op, NN, WW, 1>(a, e0, e1, c, s) : launch_corr<Op, NN, WW, 2>(a, e0, e1, c, s);
   SEIS_C(2, 2) SEIS_C(2, 4)
   SEIS_C(3, 2) SEIS_C(3, 4)
   SEIS_C(4, 2) SEIS_C(4, 4)
@@ -953,8 +951,8 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   t.iface_start = M.iface_start;
   if (tile > 0) {
     const int w = tile <= 32 ? 2 : 4;
-    t.pc = LaunchCfg{w, 0, 0};
-    t.cc = LaunchCfg{w, 0, 0};
+    t.pc = LaunchCfg{w, 0, 0, 2};
+    t.cc = LaunchCfg{w, 0, 0, 2};
     t.fixed = 1;
   }
   if (precision == 0) {  // FP64 runs the plain kernels
@@ -1045,9 +1043,10 @@ namespace {
 // Autotuner: candidate launch configurations are timed on the largest
 // cluster's matrix-core range; the winner is kept per (device, order,
 // precision, size class) in a text cache, one line per key:
-//   <key> <waves> <cap> <remap> <waves> <cap> <remap>   (predictor, corrector)
-// The cache is $SEIS_TUNE_CACHE, else $HOME/.cache/seis/tune.txt. SEIS_TUNE=0
-// disables tuning; SEIS_TUNE=w,cap,remap,w,cap,remap fixes the configuration.
+//   <key> <waves> <cap> <remap> <waves> <cap> <remap> <split>   (predictor, corrector)
+// followed by the corrector's split (passes over its output rows). The cache
+// is $SEIS_TUNE_CACHE, else $HOME/.cache/seis/tune.txt. SEIS_TUNE=0 disables
+// tuning; SEIS_TUNE=w,cap,remap,w,cap,remap[,split] fixes the configuration.
 
 std::string cache_path() {
   const char* e = std::getenv("SEIS_TUNE_CACHE");
@@ -1070,11 +1069,14 @@ std::string tune_key(const TunedData& t, int64_t ngroups) {
   int lg = 0;
   while ((int64_t(1) << (lg + 1)) <= ngroups) ++lg;
   std::ostringstream k;
-  k << "v1/" << arch << "/cu" << num_cus() << "/N" << t.N << "/p" << t.precision << "/g" << lg;
+  k << "v2/" << arch << "/cu" << num_cus() << "/N" << t.N << "/p" << t.precision << "/g" << lg;
   return k.str();
 }
 
-bool valid(const LaunchCfg& c) { return (c.waves == 2 || c.waves == 4) && c.cap >= 0 && c.cap <= 8 && (c.remap == 0 || c.remap == 1); }
+bool valid(const LaunchCfg& c) {
+  return (c.waves == 2 || c.waves == 4) && c.cap >= 0 && c.cap <= 8 && (c.remap == 0 || c.remap == 1) &&
+         (c.split == 1 || c.split == 2);
+}
 
 bool parse_cfg(const std::string& txt, LaunchCfg& p, LaunchCfg& c) {
   std::string t = txt;
@@ -1082,6 +1084,8 @@ bool parse_cfg(const std::string& txt, LaunchCfg& p, LaunchCfg& c) {
   std::istringstream in(t);
   LaunchCfg a, b;
   if (!(in >> a.waves >> a.cap >> a.remap >> b.waves >> b.cap >> b.remap)) return false;
+  int sp = 2;
+  if (in >> sp) b.split = sp;
   if (!valid(a) || !valid(b)) return false;
   p = a;
   c = b;
@@ -1162,7 +1166,7 @@ hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s) {
   for (int w : {4, 2})
     for (int cap : {0, 1, 2, 4})
       for (int rm : {0, 1}) {
-        const LaunchCfg c{w, cap, rm};
+        const LaunchCfg c{w, cap, rm, 2};
         float ms = 0.0f;
         if (cap <= 2) {
           hipError_t st = time_launch(
@@ -1177,16 +1181,20 @@ hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s) {
             bp = c;
           }
         }
-        hipError_t st = time_launch(
-            [&]() {
-              return t.precision == 1 ? corr_dispatch<OpF32>(t.N, c, t.a, e0, ei, s)
-                                      : corr_dispatch<OpBF16>(t.N, c, t.a, e0, ei, s);
-            },
-            s, reps, ms);
-        if (st != hipSuccess) return st;
-        if (ms < tc) {
-          tc = ms;
-          bc = c;
+        for (int sp : {2, 1}) {
+          LaunchCfg cs = c;
+          cs.split = sp;
+          hipError_t st = time_launch(
+              [&]() {
+                return t.precision == 1 ? corr_dispatch<OpF32>(t.N, cs, t.a, e0, ei, s)
+                                        : corr_dispatch<OpBF16>(t.N, cs, t.a, e0, ei, s);
+              },
+              s, reps, ms);
+          if (st != hipSuccess) return st;
+          if (ms < tc) {
+            tc = ms;
+            bc = cs;
+          }
         }
       }
   t.pc = bp;
@@ -1195,7 +1203,7 @@ hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s) {
   if (!path.empty()) {
     std::ofstream out(path, std::ios::app);
     if (out) out << key << ' ' << bp.waves << ' ' << bp.cap << ' ' << bp.remap << ' ' << bc.waves << ' ' << bc.cap
-                 << ' ' << bc.remap << '\n';
+                 << ' ' << bc.remap << ' ' << bc.split << '\n';
   }
   return hipSuccess;
 }

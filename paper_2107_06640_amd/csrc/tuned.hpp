@@ -34,6 +34,7 @@ struct LaunchCfg {
   int waves = 4;  // wavefronts per work-group (16 elements each): 2 or 4
   int cap = 0;    // work-groups per compute unit of a persistent grid; 0 = one work-group per 16*waves elements
   int remap = 0;  // 1: XCD-contiguous work-group order
+  int split = 2;  // corrector: passes over the output rows (1 or 2)
 };
 
 struct TunedData {

@@ -1,9 +1,12 @@
 """Autotuned launch configurations of the matrix-core kernels.
 
 The tuner times predictor and corrector launch configurations (wavefronts per
-work-group, persistent-grid size, XCD-contiguous order) at set-up and keeps
-the fastest in a cache file. Every configuration computes each 16-element
-group the same way, so results must agree bit for bit across configurations.
+work-group, persistent-grid size, XCD-contiguous order, the corrector's
+passes over its output rows) at set-up and keeps the fastest in a cache file.
+Every configuration performs the same products in the same order per output,
+but the compiled instruction streams differ, so results agree to rounding:
+per-field relative L2 below 2e-6 (FP32, a tenth of the FP32 parity bar) or
+1e-3 (BF16, where a changed last bit can flip an operand's BF16 rounding).
 """
 import numpy as np
 import pytest
@@ -37,9 +40,9 @@ def test_autotune_measures_then_reads_cache(tmp_path, monkeypatch):
     _, i1 = run(mesh, mats, "fp32", steps=0)
     assert i1["launch_source"] == 1
     w, cap, rm = i1["launch"][:3]
-    assert w in (2, 4) and 0 <= cap <= 8 and rm in (0, 1)
+    assert w in (2, 4) and 0 <= cap <= 8 and rm in (0, 1) and i1["launch"][6] in (1, 2)
     lines = cache.read_text().splitlines()
-    assert len(lines) == 1 and "/N5/p1/" in lines[0]
+    assert len(lines) == 1 and "/N5/p1/" in lines[0] and len(lines[0].split()) == 8
     _, i2 = run(mesh, mats, "fp32", steps=0)
     assert i2["launch_source"] == 2 and i2["launch"] == i1["launch"]
     _, i3 = run(mesh, mats, "bf16", steps=0)   # another key: measured again
@@ -48,18 +51,23 @@ def test_autotune_measures_then_reads_cache(tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_launch_configurations_agree_bitwise(tmp_path, monkeypatch, precision):
+def test_launch_configurations_agree(tmp_path, monkeypatch, precision):
     mesh, mats = box()
     monkeypatch.setenv("SEIS_TUNE_CACHE", str(tmp_path / "tune.txt"))
     outs = []
-    for cfg in ("4,0,0,4,0,0", "2,1,1,2,2,1", "4,2,1,2,4,0", None):
+    for cfg in ("4,0,0,4,0,0,2", "2,1,1,2,2,1,1", "4,2,1,2,4,0,2", "2,0,0,4,1,1,1", None):
         if cfg is None:
             monkeypatch.delenv("SEIS_TUNE", raising=False)
         else:
             monkeypatch.setenv("SEIS_TUNE", cfg)
         d, inf = run(mesh, mats, precision)
         if cfg is not None:
-            assert inf["launch"] == [int(x) for x in cfg.split(",")] and inf["launch_source"] == 0
+            assert inf["launch"][:7] == [int(x) for x in cfg.split(",")] and inf["launch_source"] == 0
         outs.append(d)
+    tol = 2e-6 if precision == "fp32" else 1e-3
+    ref = outs[0]
+    nrm = np.sqrt((ref ** 2).sum(axis=(0, 1)))
     for d in outs[1:]:
-        assert np.array_equal(d, outs[0])
+        rel = np.sqrt(((d - ref) ** 2).sum(axis=(0, 1))) / nrm
+        print(precision, "max field difference", rel.max())
+        assert rel.max() < tol
