@@ -216,10 +216,16 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
   if constexpr (std::is_same<Op, OpF32>::value) {
     constexpr int D = PIPE ? SEIS_PREFETCH : 0;  // rows requested ahead
     float b[D + 1][9];
+    float an[2][MT];  // A fragments of this row and the next (read from LDS one row ahead)
     auto valid = [&](int i) { return i < 4 * NT && 16 * (i >> 2) + (i & 3) < nrows; };
+    auto load_a = [&](int i, float(&dst)[MT]) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) dst[mt] = A.at(16 * mt + el, 16 * (i >> 2) + 4 * g + (i & 3));
+    };
 #pragma unroll
     for (int j = 0; j < D; ++j)
       if (valid(j)) rowfn(j >> 2, j & 3, b[j % (D + 1)]);
+    if constexpr (PIPE) load_a(0, an[0]);
 #pragma unroll
     for (int i = 0; i < 4 * NT; ++i) {
       const int t = i >> 2, v = i & 3;
@@ -227,13 +233,14 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
       float(&cur)[9] = b[i % (D + 1)];
       if constexpr (PIPE) {
         if (valid(i + D)) rowfn((i + D) >> 2, (i + D) & 3, b[(i + D) % (D + 1)]);
+        if (valid(i + 1)) load_a(i + 1, an[(i + 1) & 1]);
       } else {
         rowfn(t, v, cur);
+        load_a(i, an[i & 1]);
       }
-      const int k = 16 * t + 4 * g + v;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        const float a = A.at(16 * mt + el, k);
+        const float a = an[i & 1][mt];
 #pragma unroll
         for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, cur[p], acc[mt][p], 0, 0, 0);
       }
@@ -241,9 +248,15 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
     }
   } else {
     float bv[2][4][9];
+    s4 an[2][MT];  // A fragments of this row tile and the next
+    auto load_a = [&](int t, s4(&dst)[MT]) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) dst[mt] = A.at4(16 * mt + el, 16 * t + 4 * g);
+    };
     if constexpr (PIPE) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) rowfn(0, v, bv[0][v]);
+      load_a(0, an[0]);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -253,18 +266,19 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
         if (t + 1 < NT && 16 * (t + 1) < nrows) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) rowfn(t + 1, v, bv[(t + 1) & 1][v]);
+          load_a(t + 1, an[(t + 1) & 1]);
         }
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) rowfn(t, v, cur[v]);
+        load_a(t, an[t & 1]);
       }
       s4 b[9];
 #pragma unroll
       for (int p = 0; p < 9; ++p) b[p] = pack4(cur[0][p], cur[1][p], cur[2][p], cur[3][p]);
-      const int k0 = 16 * t + 4 * g;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
-        const s4 a = A.at4(16 * mt + el, k0);
+        const s4 a = an[t & 1][mt];
 #pragma unroll
         for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], acc[mt][p], 0, 0, 0);
       }
@@ -314,27 +328,37 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
   for (int mt = 0; mt < RTO; ++mt)
 #pragma unroll
     for (int p = 0; p < NP; ++p) acc[mt][p] = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (std::is_same<Op, OpF32>::value) {
+    // slabs (d, row) in order; the K^d fragments of the next slab are read from
+    // LDS while the products of the current one run
+    const View<float, L::ldK, true> A0(lds + L::oK), A1(lds + L::oK + L::B * L::ldK),
+        A2(lds + L::oK + 2 * L::B * L::ldK);  // A(m, l) = K^d[l][m]
+    constexpr int NV = (nin / 16) * 4 + ((nin % 16) < 4 ? (nin % 16) : 4);  // rows (t, v) with 16t + v < nin
+    float an[2][RTO];
+    auto load_a = [&](int s, float(&dst)[RTO]) {
+      const int d = s / NV, i = s % NV, k = 16 * (i >> 2) + 4 * g + (i & 3);
+#pragma unroll
+      for (int mt = 0; mt < RTO; ++mt)
+        dst[mt] = d == 0 ? A0.at(16 * mt + el, k) : (d == 1 ? A1.at(16 * mt + el, k) : A2.at(16 * mt + el, k));
+    };
+    load_a(0, an[0]);
+#pragma unroll
+    for (int s = 0; s < 3 * NV; ++s) {
+      const int d = s / NV, i = s % NV, t = i >> 2, v = i & 3;
+      if (s + 1 < 3 * NV) load_a(s + 1, an[(s + 1) & 1]);
+      float z[9];
+      apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z);
+#pragma unroll
+      for (int mt = 0; mt < RTO; ++mt) {
+        const float af = an[s & 1][mt];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, z[P0 + p], acc[mt][p], 0, 0, 0);
+      }
+    }
+  } else {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    if constexpr (std::is_same<Op, OpF32>::value) {
-      const View<float, L::ldK, true> A(lds + L::oK + d * L::B * L::ldK);  // A(m, l) = K^d[l][m]
-#pragma unroll
-      for (int t = 0; t < RTI; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (16 * t + v >= nin) continue;
-          float z[9];
-          apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z);
-          const int k = 16 * t + 4 * g + v;
-#pragma unroll
-          for (int mt = 0; mt < RTO; ++mt) {
-            const float af = A.at(16 * mt + el, k);
-#pragma unroll
-            for (int p = 0; p < NP; ++p)
-              acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, z[P0 + p], acc[mt][p], 0, 0, 0);
-          }
-        }
-    } else {
+    {
       const View<unsigned short, L::ldT, false> A(lds + L::oT + d * L::B1 * L::ldT);  // (K^d)^T[m][l]
 #pragma unroll
       for (int t = 0; t < RTI; ++t) {
@@ -355,6 +379,7 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
         }
       }
     }
+  }
   }
 #pragma unroll
   for (int mt = 0; mt < RTO; ++mt)
@@ -473,11 +498,23 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
 #pragma unroll
     for (int j = 0; j < D; ++j)
       if (valid(j)) rowfn(j >> 2, j & 3, xb[j % (D + 1)]);
+    float an[2][3][RT];  // K^d fragments of this row and the next
+    auto load_a = [&](int i, float(&dst)[3][RT]) {
+      const int k = 16 * (i >> 2) + 4 * g + (i & 3);
+#pragma unroll
+      for (int mt = 0; mt < RT; ++mt) {
+        dst[0][mt] = A0.at(16 * mt + el, k);
+        dst[1][mt] = A1.at(16 * mt + el, k);
+        dst[2][mt] = A2.at(16 * mt + el, k);
+      }
+    };
+    load_a(0, an[0]);
 #pragma unroll
     for (int i = 0; i < 4 * RT1; ++i) {
       const int t = i >> 2, v = i & 3;
       if (!valid(i)) continue;
       if (valid(i + D)) rowfn((i + D) >> 2, (i + D) & 3, xb[(i + D) % (D + 1)]);
+      if (valid(i + 1)) load_a(i + 1, an[(i + 1) & 1]);
       const float(&x)[9] = xb[i % (D + 1)];
       const bool ok = 16 * t + 4 * g + v < B1;
       float z[3][9];
@@ -487,10 +524,9 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
 #pragma unroll
         for (int p = 0; p < 9; ++p) z[d][p] = ok ? z[d][p] : 0.0f;
       }
-      const int k = 16 * t + 4 * g + v;
 #pragma unroll
       for (int mt = 0; mt < RT; ++mt) {
-        const float a0 = A0.at(16 * mt + el, k), a1 = A1.at(16 * mt + el, k), a2 = A2.at(16 * mt + el, k);
+        const float a0 = an[i & 1][0][mt], a1 = an[i & 1][1][mt], a2 = an[i & 1][2][mt];
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
           dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, z[0][p], dq[mt][p], 0, 0, 0);
