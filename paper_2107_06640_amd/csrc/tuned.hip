@@ -594,6 +594,17 @@ __device__ __forceinline__ int64_t logical_block(int remap) {
   return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
+// The predictor keeps I~ in an LDS slice per wavefront, in BF16, when the
+// operands are BF16 (the products round it to BF16 anyway) and the slices fit
+// beside the reference block; otherwise I~ is parked in HBM.
+template <class Op, int N, int W>
+struct PredLds {
+  using L = Lay<Op, N>;
+  static constexpr int slice = L::RT * 36 * 64;  // BF16 values per wavefront
+  static constexpr bool park_lds = L::BF && L::bytes + W * slice * 2 <= 160 * 1024;
+  static constexpr int bytes = L::bytes + (park_lds ? W * slice * 2 : 0);
+};
+
 template <class Op, int N, int W>
 __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, int64_t e1, int parity, int remap) {
   using L = Lay<Op, N>;
@@ -627,6 +638,9 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     // registers are free for the face and volume phases, which stream I~
     // back (mostly from L2).
     float* Ig = a.Ib + grp * (int64_t)(RT * 36 * 64);
+    // I~ parked in this wavefront's LDS slice (BF16) or in HBM (see PredLds)
+    constexpr bool LP = PredLds<Op, N, W>::park_lds;
+    unsigned short* ilds = reinterpret_cast<unsigned short*>(lds_raw + L::bytes) + w * PredLds<Op, N, W>::slice;
     {
       float J[RT1][4][9];
       CK<Op, N>::run(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
@@ -644,7 +658,10 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
           for (int p = 0; p < 9; ++p) {
             float y = x[v * 9 + p];
             if (t < RT1) y += J[t < RT1 ? t : 0][v][p];
-            ib.st((t * 4 + v) * 9 + p, y);
+            if constexpr (LP)
+              ilds[((t * 4 + v) * 9 + p) * 64 + lane] = f2bf(y);
+            else
+              ib.st((t * 4 + v) * 9 + p, y);
           }
       }
     }
@@ -662,7 +679,12 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
       const GroupBuf ib(ip, RT * 36 * 256, lane);
       return [=](int t, int v, float (&b)[9]) {
 #pragma unroll
-        for (int p = 0; p < 9; ++p) b[p] = ib.ld((t * 4 + v) * 9 + p);
+        for (int p = 0; p < 9; ++p) {
+          if constexpr (LP)
+            b[p] = __uint_as_float((unsigned)ilds[((t * 4 + v) * 9 + p) * 64 + lane] << 16);
+          else
+            b[p] = ib.ld((t * 4 + v) * 9 + p);
+        }
       };
     };
 
@@ -874,15 +896,18 @@ hipError_t prep(KernelPtr k, int lds) {
   return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
+
 template <class Op, int N, int W>
 hipError_t launch_pred(const TArgs& a, int64_t e0, int64_t e1, int parity, const LaunchCfg& c, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
   using L = Lay<Op, N>;
   const int64_t ng = ((e1 - 1) >> 4) - (e0 >> 4) + 1;
   const unsigned grid = grid_size(ng, W, c.cap);
-  static hipError_t attr = prep(k_predict_tuned<Op, N, W>, L::bytes);
+  constexpr int lds = PredLds<Op, N, W>::bytes;
+  static_assert(lds <= 160 * 1024, "predictor LDS exceeds the 160 KB of a CU");
+  static hipError_t attr = prep(k_predict_tuned<Op, N, W>, lds);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_predict_tuned<Op, N, W>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1, parity, c.remap);
+  hipLaunchKernelGGL((k_predict_tuned<Op, N, W>), dim3(grid), dim3(64 * W), lds, s, a, e0, e1, parity, c.remap);
   return hipGetLastError();
 }
 
