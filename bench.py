@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--scale", type=int, default=1)
     ap.add_argument("--max-clusters", type=int, default=4)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--mc-min", type=int, default=None,
+                    help="clusters with fewer elements run on the plain FP32 kernels (library default 2048)")
     ap.add_argument("--graph", action="store_true",
                     help="replay each macro step as one hipGraph; kernel timings then come from a "
                          "separate eagerly launched pass of the same length")
@@ -258,7 +260,7 @@ def main():
     stream = torch.cuda.Stream()
     s = seis.from_mesh(mesh, mats, args.order, precision=args.precision, kernel=args.kernel,
                        max_clusters=args.max_clusters, stream=stream.cuda_stream, tile=args.tile,
-                       graph=args.graph)
+                       graph=args.graph, mc_min=args.mc_min)
     inf = s.info()
     q = tiled_dofs(mesh.n_elements, inf["n_basis"], 0, mu == 0)
     s.write(q)
@@ -336,6 +338,7 @@ def main():
                    "kernel": args.kernel, "precision": args.precision, "elements": inf["n_elements"],
                    "graph": bool(args.graph), "eager_ms_per_step": eager_ms / args.steps,
                    "launch": {"predict": inf["launch"][:3], "correct": inf["launch"][3:7],
+                              "mc_min": inf["launch"][7],
                               "source": ["default", "measured", "cache"][inf["launch_source"]]},
                    "updates_per_step": inf["updates_per_macro_step"]},
         "roofline": roof,

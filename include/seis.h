@@ -103,6 +103,11 @@ typedef struct {
                        fixes it. */
   int graph;        /* nonzero: seis_step captures its macro step into a hipGraph at its first
                        call and replays that graph afterwards (one launch per macro step) */
+  int mc_min;       /* tuned kernels, FP32/BF16: a cluster with fewer elements than this runs on
+                       the plain FP32 kernels instead of the matrix cores (a matrix-core
+                       wavefront works through its 16 elements in sequence, so a tiny cluster is
+                       bound by that latency there). Default 2048; 0 puts every cluster on the
+                       matrix cores. Must be >= 0. */
 } seis_options_t;
 
 typedef struct {
@@ -123,13 +128,13 @@ typedef struct {
   int launch[8];        /* matrix-core launch configuration of the predictor, then the corrector:
                            wavefronts per work-group, work-groups per CU of a persistent grid
                            (0 = one work-group per 16 x wavefronts elements), XCD-contiguous order;
-                           [6] the corrector's passes over its output rows; [7] unused (0) */
+                           [6] the corrector's passes over its output rows; [7] options.mc_min */
   int launch_source;    /* 0 default or fixed (options.tile, SEIS_TUNE), 1 measured at set-up,
                            2 read from the tuning cache */
 } seis_info_t;
 
 /* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream,
- * eager launches (no graph). */
+ * eager launches (no graph), mc_min 2048. */
 void seis_default_options(seis_options_t *opt);
 
 /* Build the solver for a mesh (Sec. 4.1-4.4): validate, match faces,

@@ -130,7 +130,7 @@ int build_dev(seis_t* h, DevData<T>& d) {
   HIPCHK(h, b.alloc(&H2, std::max<int64_t>(M.n_half2, 1) * Bf * 9), "alloc H2");
   HIPCHK(h, hipMemset(H2, 0, std::max<int64_t>(M.n_half2, 1) * Bf * 9 * sizeof(T)), "memset H2");
   const int64_t Fg = (int64_t)M.g_elem.size();
-  HIPCHK(h, b.alloc(&gD, std::max<int64_t>(Fg, 1) * (N + 1) * B * 9), "alloc gD");
+  HIPCHK(h, b.alloc(&gD, std::max<int64_t>(std::max<int64_t>(Fg, M.n_dslot), 1) * (N + 1) * B * 9), "alloc gD");
   HIPCHK(h, upload(b, &K, M.ref.K), "upload K");
   HIPCHK(h, upload(b, &Ef, M.ref.E), "upload E");
   HIPCHK(h, upload(b, &Lf, M.ref.L), "upload L");
@@ -301,7 +301,7 @@ int do_predict(seis_t* h, int c) {
       if (h->precision == SEIS_FP64) return launch_predict_plain<double>(N, h->d64, e0, ne, parity, h->stream);
       return launch_predict_plain<float>(N, h->d32, e0, ne, parity, h->stream);
     }
-    return tuned_predict(h->tuned, h->precision, N, e0, M.iface_start[c], e0 + ne, parity, h->stream);
+    return tuned_predict(h->tuned, h->precision, N, c, e0, e0 + ne, parity, h->stream);
   });
   if (st == hipSuccess)
     st = timed(h, 1, ng, [&]() -> hipError_t {
@@ -322,7 +322,7 @@ int do_correct(seis_t* h, int c) {
       if (h->precision == SEIS_FP64) return launch_correct_plain<double>(N, h->d64, e0, ne, parity, h->stream);
       return launch_correct_plain<float>(N, h->d32, e0, ne, parity, h->stream);
     }
-    return tuned_correct(h->tuned, h->precision, N, e0, M.iface_start[c], e0 + ne, parity, h->stream);
+    return tuned_correct(h->tuned, h->precision, N, c, e0, e0 + ne, parity, h->stream);
   });
   if (st != hipSuccess) return hip_fail(h, st, "correct launch");
   return SEIS_OK;
@@ -379,6 +379,7 @@ void seis_default_options(seis_options_t* o) {
   o->stream = nullptr;
   o->tile = 0;
   o->graph = 0;
+  o->mc_min = 2048;
 }
 
 int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, const seis_options_t* opt,
@@ -399,6 +400,7 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
   if (o.kernel == SEIS_KERNEL_PLAIN && o.precision == SEIS_BF16)
     return setup_fail(SEIS_EINVAL, "BF16 operands need the tuned (MFMA) kernels");
   if (order < 3 || order > 7) return setup_fail(SEIS_EINVAL, "order must be in 3..7");
+  if (o.mc_min < 0) return setup_fail(SEIS_EINVAL, "mc_min must be >= 0");
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
@@ -427,6 +429,7 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
   h->tile = o.tile;
   h->stream = (hipStream_t)o.stream;
   h->use_graph = o.graph != 0;
+  h->tuned.mc_min = o.mc_min;
   int rc = build_common(h, h->d64);
   if (rc == SEIS_OK) {
     if (o.precision == SEIS_FP64) {
@@ -697,7 +700,7 @@ int seis_info(const seis_t* h, seis_info_t* info) {
     info->launch[3 * k + 2] = lc[k]->remap;
   }
   info->launch[6] = h->tuned.cc.split;
-  info->launch[7] = 0;
+  info->launch[7] = h->tuned.mc_min;
   info->launch_source = h->tuned.source;
   return SEIS_OK;
 }

@@ -27,7 +27,6 @@ struct Model {
   double dt_min = 0.0;
   std::vector<double> dt_c;            // [C]
   std::vector<int64_t> cluster_start;  // [C+1]
-  std::vector<int64_t> iface_start;    // [C]: first element of cluster c with a neighbour in another cluster
   std::vector<int64_t> new_of_old;     // [E]
   std::vector<int64_t> old_of_new;     // [E]
   std::vector<int32_t> cluster_old;    // [E], caller order
@@ -54,6 +53,16 @@ struct Model {
   std::vector<double> g_par;           // [F_g][8]: scale 2A/|J|, n_x, n_y, n_z, Z, a = rho g / Z, lambda, dt
   std::vector<int32_t> gslot;          // [E] gravity face index of an element, -1 none
   std::vector<int64_t> g_order;        // [F_g]: ABI position of library gravity face f
+  // stored time derivatives: gravity elements use their gravity face index,
+  // elements handing over to a finer neighbour (and without a gravity face)
+  // the slots after those
+  std::vector<int32_t> dslot;          // [E] derivative slot, -1 none
+  int64_t n_dslot = 0;
+  // per cluster c, entries [start[c], start[c+1]) of element * 4 + face:
+  std::vector<int32_t> fix_list;       // faces handing over to a finer neighbour (MODE_FINER)
+  std::vector<int64_t> fix_start;      // [C+1]
+  std::vector<int32_t> h2_list;        // faces that read a second-half slot on odd sub-steps
+  std::vector<int64_t> h2_start;       // [C+1]
   double g = 9.81;
 
   RefElement ref;

@@ -277,7 +277,8 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
   M.cluster_old = cl;
 
   // ---- element order: by cluster; inside a cluster, elements with a
-  // neighbour in another cluster last (stable)
+  // neighbour in another cluster last (stable), so that the hand-over branches
+  // of the matrix-core kernels diverge in few element groups
   std::vector<int8_t> iface(E, 0);
   for (int64_t id = 0; id < E * 4; ++id)
     if (nb[id] >= 0 && cl[nb[id] / 4] != cl[id / 4]) iface[id / 4] = 1;
@@ -292,12 +293,6 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
   M.cluster_start.assign(C + 1, 0);
   for (int64_t e = 0; e < E; ++e) M.cluster_start[cl[e] + 1]++;
   for (int c = 0; c < C; ++c) M.cluster_start[c + 1] += M.cluster_start[c];
-  M.iface_start.assign(C, 0);
-  for (int c = 0; c < C; ++c) {
-    int64_t k = M.cluster_start[c];
-    while (k < M.cluster_start[c + 1] && !iface[M.old_of_new[k]]) ++k;
-    M.iface_start[c] = k;
-  }
 
   // ---- per element inputs of the operator assembly (new order)
   M.a_Jinv.resize(E * 9);
@@ -371,6 +366,30 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
       }
   M.g_order.resize(M.g_elem.size());
   std::iota(M.g_order.begin(), M.g_order.end(), 0);
+
+  // ---- derivative slots and the per-cluster face lists of the LTS hand-over
+  M.dslot.assign(E, -1);
+  int64_t nd = (int64_t)M.g_elem.size();
+  for (int64_t k = 0; k < E; ++k) M.dslot[k] = M.gslot[k];
+  for (int64_t k = 0; k < E; ++k) {
+    bool finer = false;
+    for (int f = 0; f < 4; ++f) finer = finer || M.mode[k * 4 + f] == MODE_FINER;
+    if (finer && M.dslot[k] < 0) M.dslot[k] = int32_t(nd++);
+  }
+  M.n_dslot = nd;
+  M.fix_start.assign(C + 1, 0);
+  M.h2_start.assign(C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    M.fix_start[c] = (int64_t)M.fix_list.size();
+    M.h2_start[c] = (int64_t)M.h2_list.size();
+    for (int64_t k = M.cluster_start[c]; k < M.cluster_start[c + 1]; ++k)
+      for (int f = 0; f < 4; ++f) {
+        if (M.mode[k * 4 + f] == MODE_FINER) M.fix_list.push_back(int32_t(k * 4 + f));
+        if (M.rhalf2[k * 4 + f] >= 0) M.h2_list.push_back(int32_t(k * 4 + f));
+      }
+  }
+  M.fix_start[C] = (int64_t)M.fix_list.size();
+  M.h2_start[C] = (int64_t)M.h2_list.size();
   return "";
 }
 

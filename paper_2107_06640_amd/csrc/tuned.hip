@@ -619,7 +619,6 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int el = lane & 15, g = lane >> 4;
   const int64_t gfirst = e0 >> 4, glast = (e1 - 1) >> 4;
-  (void)parity;  // every face here hands over a full-step trace
   for (int64_t grp = gfirst + logical_block(remap) * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
     const int64_t e = grp * 16 + el;
     const bool live = e >= e0 && e < e1;
@@ -629,7 +628,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     for (int i = 0; i < 9; ++i) G[i] = a.G[ec * 9 + i];
     const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
     const float* Qg = a.Q + grp * (int64_t)(RT * 36 * 64);
-    const int gs0 = a.gslot[ec];
+    const int gs0 = a.dslot[ec];
     const int gs = live ? gs0 : -1;
     float* gd = gs >= 0 ? a.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
 
@@ -708,15 +707,19 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
           for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? va[t][p][v] : 0.0f;
         }
-      // hand-over: these elements have all face neighbours in their own
-      // cluster (the others run on the plain kernels), so every paired face
-      // receives the full-step trace. Loads are unconditional (valid indices
-      // for every lane); only the stores are masked.
+      // hand-over into the neighbour's inbox (its node numbering, its time
+      // step): a neighbour in the same cluster gets the full-step trace; a
+      // coarser one half of it, accumulated over this element's two steps
+      // (parity is uniform over the launch); a finer one gets the full-step
+      // trace here, which the half-step fix-up turns into its two halves.
+      // Loads are unconditional (valid indices for every lane); only the
+      // stores are masked.
       {
         const int md0 = a.mode[ec * 4 + f];
         const int32_t tg0 = a.tgt[ec * 4 + f];
         const int h = a.hperm[ec * 4 + f];
         const bool send = live && md0 != 0;
+        const bool half = md0 == 3;
         const int32_t tg = send ? tg0 : 0;
 #pragma unroll
         for (int t = 0; t < FT; ++t)
@@ -728,11 +731,17 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
             for (int p = 0; p < 9; ++p) {
               float* dst = a.In + inidx(tg >> 2, tg & 3, mr, p, FT);
+              if (half && parity) {
+                // second step of the pair: add to the first half (one writer per
+                // slot; a no-return atomic keeps the load out of this kernel)
+                atomicAdd(dst, 0.5f * V[t][v][p]);
+              } else {
 #if SEIS_NT_STORE
-              __builtin_nontemporal_store(V[t][v][p], dst);
+                __builtin_nontemporal_store(half ? 0.5f * V[t][v][p] : V[t][v][p], dst);
 #else
-              *dst = V[t][v][p];
+                *dst = half ? 0.5f * V[t][v][p] : V[t][v][p];
 #endif
+              }
             }
           }
       }
@@ -868,6 +877,96 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
       }
     }
   }
+}
+
+// Half-step fix-up of the faces handing over to a finer neighbour (one
+// work-group per face of list): the predictor wrote the full-step trace V;
+// the finer neighbour needs the traces of the first and of the second half of
+// this element's step, each over its own step: the first half
+// h1 = E_f I~_h with I~_h = sum_k D~k 2^-k / (k+1) (from the stored
+// derivatives) goes to the inbox, the second half 2 V - h1 to its slot.
+template <int N>
+__global__ __launch_bounds__(64) void k_finer_fixup(TArgs a, const int32_t* list) {
+  constexpr int B = nbasis(N), Bf = nface(N), FT = row_tiles(Bf);
+  __shared__ float sIh[B * 9];
+  const int id = list[blockIdx.x];
+  const int64_t e = id >> 2;
+  const int f = id & 3;
+  const float* D = a.gD + (int64_t)a.dslot[e] * (N + 1) * B * 9;
+  for (int i = threadIdx.x; i < B * 9; i += 64) {
+    float acc = 0.0f, w = 1.0f;
+    for (int k = 0; k <= N; ++k) {
+      acc += w / float(k + 1) * D[k * B * 9 + i];
+      w *= 0.5f;
+    }
+    sIh[i] = acc;
+  }
+  __syncthreads();
+  const int32_t tg = a.tgt[e * 4 + f];
+  const int h = a.hperm[e * 4 + f];
+  const int slot = a.half2[e * 4 + f];
+  for (int i = threadIdx.x; i < Bf * 9; i += 64) {
+    const int m = i / 9, p = i % 9;
+    const float* Em = a.Ef + ((int64_t)f * Bf + m) * B;
+    float h1 = 0.0f;
+    for (int l = 0; l < B; ++l) h1 += Em[l] * sIh[l * 9 + p];
+    const int mr = a.pinv[h * Bf + m];
+    float* dst = a.In + inidx(tg >> 2, tg & 3, mr, p, FT);
+    const float v = *dst;
+    *dst = h1;
+    a.H2[((int64_t)slot * Bf + mr) * 9 + p] = 2.0f * v - h1;
+  }
+}
+
+// Second-half traces into the inbox before the corrector of an odd sub-step
+// (one work-group per face of list).
+template <int N>
+__global__ __launch_bounds__(64) void k_h2_to_in(TArgs a, const int32_t* list) {
+  constexpr int Bf = nface(N), FT = row_tiles(Bf);
+  const int id = list[blockIdx.x];
+  const int64_t e = id >> 2;
+  const int f = id & 3;
+  const int slot = a.rhalf2[e * 4 + f];
+  for (int i = threadIdx.x; i < Bf * 9; i += 64) {
+    const int m = i / 9, p = i % 9;
+    a.In[inidx(e, f, m, p, FT)] = a.H2[((int64_t)slot * Bf + m) * 9 + p];
+  }
+}
+
+template <int N>
+hipError_t launch_fixup(const TArgs& a, const int32_t* list, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finer_fixup<N>, dim3((unsigned)n), dim3(64), 0, s, a, list);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_h2(const TArgs& a, const int32_t* list, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_h2_to_in<N>, dim3((unsigned)n), dim3(64), 0, s, a, list);
+  return hipGetLastError();
+}
+
+hipError_t fixup_dispatch(int N, const TArgs& a, const int32_t* list, int64_t n, hipStream_t s) {
+  switch (N) {
+    case 2: return launch_fixup<2>(a, list, n, s);
+    case 3: return launch_fixup<3>(a, list, n, s);
+    case 4: return launch_fixup<4>(a, list, n, s);
+    case 5: return launch_fixup<5>(a, list, n, s);
+    case 6: return launch_fixup<6>(a, list, n, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t h2_dispatch(int N, const TArgs& a, const int32_t* list, int64_t n, hipStream_t s) {
+  switch (N) {
+    case 2: return launch_h2<2>(a, list, n, s);
+    case 3: return launch_h2<3>(a, list, n, s);
+    case 4: return launch_h2<4>(a, list, n, s);
+    case 5: return launch_h2<5>(a, list, n, s);
+    case 6: return launch_h2<6>(a, list, n, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 int g_num_cus = 0;
@@ -1009,7 +1108,8 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   t.precision = precision;
   t.d64 = d64;
   t.d32 = d32;
-  t.iface_start = M.iface_start;
+  t.fix_start = M.fix_start;
+  t.h2_start = M.h2_start;
   if (tile > 0) {
     const int w = tile <= 32 ? 2 : 4;
     t.pc = LaunchCfg{w, 0, 0, 2};
@@ -1028,7 +1128,10 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   a.tgt = d32.tgt;
   a.mode = d32.mode;
   a.hperm = d32.hperm;
-  a.gslot = d32.gslot;
+  a.Ef = d32.Ef;
+  a.H2 = d32.H2;
+  a.half2 = d32.half2;
+  a.rhalf2 = d32.rhalf2;
   a.gD = d32.gD;
   {
     const int64_t nJ = q_size(M.E, row_tiles(n_basis(M.N)));
@@ -1057,6 +1160,16 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   a.RCm = rcm;
   a.RCp = rcp;
   a.pinv = pinv;
+  {
+    int32_t *ds, *fl, *hl;
+    st = upload(owned, bytes, &ds, M.dslot);
+    if (st == hipSuccess) st = upload(owned, bytes, &fl, M.fix_list);
+    if (st == hipSuccess) st = upload(owned, bytes, &hl, M.h2_list);
+    if (st != hipSuccess) return st;
+    a.dslot = ds;
+    a.fix_list = fl;
+    a.h2_list = hl;
+  }
   // LDS image of the reference matrices (layout of Lay<Op, N>), padded to 16 bytes
   int lbytes = 0;
   if (precision == 1) {
@@ -1079,22 +1192,28 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   return hipSuccess;
 }
 
-hipError_t tuned_predict(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
+hipError_t tuned_predict(const TunedData& t, int precision, int N, int c, int64_t e0, int64_t e1, int parity,
                          hipStream_t s) {
   if (precision == 0) return launch_predict_plain<double>(N, t.d64, e0, e1 - e0, parity, s);
-  hipError_t st = precision == 1 ? pred_dispatch<OpF32>(N, t.pc, t.a, e0, ei, parity, s)
-                                 : pred_dispatch<OpBF16>(N, t.pc, t.a, e0, ei, parity, s);
+  if (e1 - e0 < t.mc_min) return launch_predict_plain<float>(N, t.d32, e0, e1 - e0, parity, s);
+  hipError_t st = precision == 1 ? pred_dispatch<OpF32>(N, t.pc, t.a, e0, e1, parity, s)
+                                 : pred_dispatch<OpBF16>(N, t.pc, t.a, e0, e1, parity, s);
   if (st != hipSuccess) return st;
-  return launch_predict_plain<float>(N, t.d32, ei, e1 - ei, parity, s);
+  const int64_t f0 = t.fix_start[c], nf = t.fix_start[c + 1] - f0;
+  return fixup_dispatch(N, t.a, t.a.fix_list + f0, nf, s);
 }
 
-hipError_t tuned_correct(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
+hipError_t tuned_correct(const TunedData& t, int precision, int N, int c, int64_t e0, int64_t e1, int parity,
                          hipStream_t s) {
   if (precision == 0) return launch_correct_plain<double>(N, t.d64, e0, e1 - e0, parity, s);
-  hipError_t st = precision == 1 ? corr_dispatch<OpF32>(N, t.cc, t.a, e0, ei, s)
-                                 : corr_dispatch<OpBF16>(N, t.cc, t.a, e0, ei, s);
-  if (st != hipSuccess) return st;
-  return launch_correct_plain<float>(N, t.d32, ei, e1 - ei, parity, s);
+  if (e1 - e0 < t.mc_min) return launch_correct_plain<float>(N, t.d32, e0, e1 - e0, parity, s);
+  if (parity) {
+    const int64_t h0 = t.h2_start[c], nh = t.h2_start[c + 1] - h0;
+    hipError_t st = h2_dispatch(N, t.a, t.a.h2_list + h0, nh, s);
+    if (st != hipSuccess) return st;
+  }
+  return precision == 1 ? corr_dispatch<OpF32>(N, t.cc, t.a, e0, e1, s)
+                        : corr_dispatch<OpBF16>(N, t.cc, t.a, e0, e1, s);
 }
 
 
@@ -1186,18 +1305,18 @@ hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s) {
     t.source = 0;
     return hipSuccess;
   }
-  // the largest matrix-core range of any cluster
+  // the largest cluster
   int cbest = -1;
   int64_t nbest = 0;
   for (int c = 0; c < M.C; ++c) {
-    const int64_t n = M.iface_start[c] - M.cluster_start[c];
+    const int64_t n = M.cluster_start[c + 1] - M.cluster_start[c];
     if (n > nbest) {
       nbest = n;
       cbest = c;
     }
   }
-  if (cbest < 0 || nbest < 16) return hipSuccess;
-  const int64_t e0 = M.cluster_start[cbest], ei = M.iface_start[cbest];
+  if (cbest < 0 || nbest < 16 || nbest < t.mc_min) return hipSuccess;
+  const int64_t e0 = M.cluster_start[cbest], ei = M.cluster_start[cbest + 1];
   const int64_t ngroups = ((ei - 1) >> 4) - (e0 >> 4) + 1;
   const std::string key = tune_key(t, ngroups);
   const std::string path = cache_path();

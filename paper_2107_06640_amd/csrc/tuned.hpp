@@ -22,8 +22,14 @@ struct TArgs {
   const int8_t* mode;   // [E][4]
   const int8_t* hperm;  // [E][4]
   const int32_t* pinv;  // [6][Bf]
-  const int32_t* gslot; // [E]
-  float* gD;            // [F_g][N+1][B][9]
+  const int32_t* dslot; // [E] slot of the stored time derivatives, -1 none
+  float* gD;            // [slots][N+1][B][9] time derivatives (gravity faces, then hand-over to finer neighbours)
+  const float* Ef;      // [4][Bf][B] face-trace matrices (FP32)
+  float* H2;            // [n_half2][Bf][9] second-half traces for finer neighbours
+  const int32_t* half2; // [E][4] writer: second-half slot, -1 none
+  const int32_t* rhalf2;// [E][4] reader: second-half slot, -1 none
+  const int32_t* fix_list;  // element * 4 + face of the faces handing over to a finer neighbour
+  const int32_t* h2_list;   // element * 4 + face of the faces reading a second-half slot
   float* Ib;            // tiled [E][B][9]: time-integrated predictor I~ = Q + J, parked by the predictor
   const void* ref;      // reference matrices K | E | L in operand precision
   int ref_bytes;
@@ -44,21 +50,26 @@ struct TunedData {
   LaunchCfg pc{}, cc{};  // predictor, corrector
   int fixed = 0;         // configuration fixed by the caller (options.tile)
   int source = 0;        // 0 default or fixed, 1 measured at set-up, 2 read from the tuning cache
+  int64_t mc_min = 0;    // clusters with fewer elements run on the plain FP32 kernels
   TArgs a{};
-  std::vector<int64_t> iface_start;   // per cluster: first element handled by the plain kernels
+  std::vector<int64_t> fix_start, h2_start;  // per cluster: ranges of fix_list and h2_list
   DevData<double> d64{};
   DevData<float> d32{};
 };
 
 hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevData<double>& d64,
                        const DevData<float>& d32, int tile, std::vector<void*>& owned, int64_t& bytes);
-// Elements [e0, ei) go to the matrix-core kernels, [ei, e1) (neighbours in
-// another LTS cluster) to the plain kernels.
-hipError_t tuned_predict(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
+// Cluster c = elements [e0, e1). FP64 runs the plain kernels, and so does a
+// cluster of fewer than mc_min elements (in FP32). Otherwise the
+// matrix-core predictor handles every element; faces handing over to a finer
+// neighbour are then rewritten with the first- and second-half traces, and
+// before the corrector of an odd sub-step the second-half traces are copied
+// into the inbox of the finer elements that read them.
+hipError_t tuned_predict(const TunedData& t, int precision, int N, int c, int64_t e0, int64_t e1, int parity,
                          hipStream_t s);
-hipError_t tuned_correct(const TunedData& t, int precision, int N, int64_t e0, int64_t ei, int64_t e1, int parity,
+hipError_t tuned_correct(const TunedData& t, int precision, int N, int c, int64_t e0, int64_t e1, int parity,
                          hipStream_t s);
-// Choose pc and cc for the largest cluster's matrix-core range [e0, ei) by
+// Choose pc and cc for the largest cluster by
 // timing the candidates on the (zero) state left by set-up, or read them from
 // the tuning cache. The state stays zero: every kernel is linear.
 hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s);

@@ -43,7 +43,8 @@ class Materials_t(C.Structure):
 
 class Options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("kernel", C.c_int), ("cfl", C.c_double), ("g", C.c_double),
-                ("max_clusters", C.c_int), ("stream", C.c_void_p), ("tile", C.c_int), ("graph", C.c_int)]
+                ("max_clusters", C.c_int), ("stream", C.c_void_p), ("tile", C.c_int), ("graph", C.c_int),
+                ("mc_min", C.c_int)]
 
 
 class Info_t(C.Structure):
@@ -103,7 +104,8 @@ class Solver:
     """One library handle (seis_setup ... seis_destroy)."""
 
     def __init__(self, xyz, tet, face_kind, period, rho, lam, mu, order, *, precision="fp64",
-                 kernel="tuned", cfl=0.35, g=9.81, max_clusters=1, stream=None, tile=0, graph=False):
+                 kernel="tuned", cfl=0.35, g=9.81, max_clusters=1, stream=None, tile=0, graph=False,
+                 mc_min=None):
         lib = load_library()
         self._lib = lib
         self._keep = [np.ascontiguousarray(xyz, dtype=np.float64), np.ascontiguousarray(tet, dtype=np.int64),
@@ -123,6 +125,8 @@ class Solver:
         opt.stream = stream
         opt.tile = tile
         opt.graph = 1 if graph else 0
+        if mc_min is not None:
+            opt.mc_min = int(mc_min)
         h = C.c_void_p()
         rc = lib.seis_setup(C.byref(mesh), C.byref(mats), int(order), C.byref(opt), C.byref(h))
         if rc != 0:

@@ -23,7 +23,7 @@ def lts_box():
 def test_graph_replays_match_eager(precision, kernel):
     from paper_2107_06640_amd import seis
     mesh, mats = lts_box()
-    kw = dict(precision=precision, kernel=kernel, max_clusters=3)
+    kw = dict(precision=precision, kernel=kernel, max_clusters=3, mc_min=0)
     eager = seis.from_mesh(mesh, mats, 5, **kw)
     graph = seis.from_mesh(mesh, mats, 5, graph=True, **kw)
     try:
@@ -59,7 +59,7 @@ def test_graph_replays_match_eager(precision, kernel):
 def test_graph_rejects_mid_step_and_recovers():
     from paper_2107_06640_amd import seis
     mesh, mats = lts_box()
-    s = seis.from_mesh(mesh, mats, 4, precision="fp32", kernel="tuned", max_clusters=3, graph=True)
+    s = seis.from_mesh(mesh, mats, 4, precision="fp32", kernel="tuned", max_clusters=3, graph=True, mc_min=0)
     try:
         s.predict(0)
         with pytest.raises(seis.SeisError):

@@ -31,12 +31,13 @@ def say(*a):
 
 
 def run_pair(mesh, mats, order, steps, *, precision="fp64", kernel="plain", max_clusters=1, cfl=0.35,
-             g=9.81, seed=0, eta_seed=None, tile=0):
+             g=9.81, seed=0, eta_seed=None, tile=0, mc_min=0):
     wet = mats[2] == 0
     o = oracle_for(mesh, mats, order, cfl=cfl, g=g, max_clusters=max_clusters)
     s = seis().from_mesh(mesh, mats, order, precision=precision, kernel=kernel, cfl=cfl, g=g,
-                         max_clusters=max_clusters, tile=tile)
-    say(f"case: E={mesh.n_elements} order={order} steps={steps} {precision}/{kernel} C={max_clusters}")
+                         max_clusters=max_clusters, tile=tile, mc_min=mc_min)
+    say(f"case: E={mesh.n_elements} order={order} steps={steps} {precision}/{kernel} C={max_clusters} "
+        f"mc_min={mc_min}")
     assert np.array_equal(s.cluster_of(), o.cluster)
     inf = s.info()
     assert abs(inf["dt_min"] - o.dt_min) <= 1e-13 * o.dt_min
@@ -219,3 +220,23 @@ def test_tuned_tiles_agree(tile):
     mesh, mats = inputs.coupled_box(4, 3, 4, cell=500.0, water_layers=2, jitter=0.15, seed=9)
     o, d, e = run_pair(mesh, mats, 4, 1, precision="fp32", kernel="tuned", tile=tile, seed=9)
     assert field_errors(d, o.Q, o.geo.absdet).max() < TOL32
+
+
+@pytest.mark.parametrize("mc_min", [0, 160])
+@pytest.mark.parametrize("precision,tol", [("fp32", TOL32), ("bf16", TOL16)])
+def test_tuned_lts_interfaces_with_gravity(precision, tol, mc_min):
+    # three clusters (137, 185 and 158 elements) over a graded water column
+    # with a gravity surface. mc_min 0: the matrix-core kernels run every
+    # element, including those handing over to finer (half-step traces) and
+    # coarser (accumulated halves) neighbours. mc_min 160: the middle cluster
+    # runs on the matrix cores and its finer and coarser neighbours on the
+    # plain kernels, so every hand-over crosses between the two kernel kinds.
+    zn = np.array([0.0, 0.5, 0.75, 0.875, 0.9375, 1.0]) * 1000.0 - 1000.0
+    mesh, mats = inputs.coupled_box(4, 4, 5, cell=500.0, water_layers=1, z_nodes=zn, jitter=0.1, seed=2)
+    o, d, e = run_pair(mesh, mats, 5, 2, precision=precision, kernel="tuned", max_clusters=4, seed=6,
+                       mc_min=mc_min)
+    assert list(np.bincount(o.cluster)) == [137, 185, 158]
+    fe = field_errors(d, o.Q, o.geo.absdet)
+    ee = np.abs(e - o.eta).max() / np.abs(o.eta).max()
+    say(f"tuned {precision} lts+gravity field errors", np.array2string(fe, precision=3), "eta", ee)
+    assert fe.max() < tol and ee < tol
