@@ -58,13 +58,19 @@ __host__ __device__ inline unsigned short f2bf(float x) {
   return (unsigned short)(u >> 16);
 }
 
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+
+// two floats to packed BF16, round to nearest even (one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ unsigned pack2(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector(fl2{a, b}, bf2));
+}
+
+__device__ __forceinline__ unsigned short f2bf_dev(float x) { return (unsigned short)(pack2(x, 0.0f) & 0xffffu); }
+
 __device__ __forceinline__ s4 pack4(float a, float b, float c, float d) {
-  s4 r;
-  r[0] = (short)f2bf(a);
-  r[1] = (short)f2bf(b);
-  r[2] = (short)f2bf(c);
-  r[3] = (short)f2bf(d);
-  return r;
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(s4, u2{pack2(a, b), pack2(c, d)});
 }
 
 // (A_e u)_p for e = x, y, z: the three Jacobians of the velocity-stress
@@ -597,12 +603,15 @@ __device__ __forceinline__ int64_t logical_block(int remap) {
 // The predictor keeps I~ in an LDS slice per wavefront, in BF16, when the
 // operands are BF16 (the products round it to BF16 anyway) and the slices fit
 // beside the reference block; otherwise I~ is parked in HBM.
+// The node permutation table (6 x Bf entries) follows.
 template <class Op, int N, int W>
 struct PredLds {
   using L = Lay<Op, N>;
   static constexpr int slice = L::RT * 36 * 64;  // BF16 values per wavefront
-  static constexpr bool park_lds = L::BF && L::bytes + W * slice * 2 <= 160 * 1024;
-  static constexpr int bytes = L::bytes + (park_lds ? W * slice * 2 : 0);
+  static constexpr int perm_bytes = (6 * L::Bf * 4 + 15) / 16 * 16;
+  static constexpr bool park_lds = L::BF && L::bytes + W * slice * 2 + perm_bytes <= 160 * 1024;
+  static constexpr int perm_off = L::bytes + (park_lds ? W * slice * 2 : 0);
+  static constexpr int bytes = perm_off + perm_bytes;
 };
 
 template <class Op, int N, int W>
@@ -613,6 +622,8 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const R* lds = reinterpret_cast<const R*>(lds_raw);
   stage_ref<Op>(lds_raw, a.ref, L::bytes, 64 * W);
+  int* perm = reinterpret_cast<int*>(lds_raw + PredLds<Op, N, W>::perm_off);
+  for (int i = threadIdx.x; i < 6 * Bf; i += 64 * W) perm[i] = a.pinv[i];
   __syncthreads();
   // the wavefront index is uniform across the wavefront: keep it (and every
   // group base and buffer descriptor derived from it) in scalar registers
@@ -623,6 +634,10 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     const int64_t e = grp * 16 + el;
     const bool live = e >= e0 && e < e1;
     const int64_t ec = live ? e : e0;
+    // hand-over descriptors of the four faces: targets, and mode | orientation << 2 per byte
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 tg4 = *reinterpret_cast<const i4*>(a.tgt + ec * 4);
+    const int mh = a.mh4[ec];
     float G[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) G[i] = a.G[ec * 9 + i];
@@ -658,7 +673,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
             float y = x[v * 9 + p];
             if (t < RT1) y += J[t < RT1 ? t : 0][v][p];
             if constexpr (LP)
-              ilds[((t * 4 + v) * 9 + p) * 64 + lane] = f2bf(y);
+              ilds[((t * 4 + v) * 9 + p) * 64 + lane] = f2bf_dev(y);
             else
               ib.st((t * 4 + v) * 9 + p, y);
           }
@@ -691,6 +706,10 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     // loop: unrolled, the four faces' live ranges overlap and spill.
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
+      // this face's flux coefficients, requested before the trace products
+      float c[11];
+#pragma unroll
+      for (int i = 0; i < 11; ++i) c[i] = a.RCm[(ec * 4 + f) * 12 + i];
       f4 va[FT][9];
 #pragma unroll
       for (int t = 0; t < FT; ++t)
@@ -715,9 +734,9 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
       // Loads are unconditional (valid indices for every lane); only the
       // stores are masked.
       {
-        const int md0 = a.mode[ec * 4 + f];
-        const int32_t tg0 = a.tgt[ec * 4 + f];
-        const int h = a.hperm[ec * 4 + f];
+        const int md0 = (mh >> (8 * f)) & 3;
+        const int32_t tg0 = f == 0 ? tg4[0] : (f == 1 ? tg4[1] : (f == 2 ? tg4[2] : tg4[3]));
+        const int h = (mh >> (8 * f + 2)) & 7;
         const bool send = live && md0 != 0;
         const bool half = md0 == 3;
         const int32_t tg = send ? tg0 : 0;
@@ -726,7 +745,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int node = 16 * t + 4 * g + v;
-            const int mr = a.pinv[h * Bf + (node < Bf ? node : Bf - 1)];
+            const int mr = perm[h * Bf + (node < Bf ? node : Bf - 1)];
             if (!send || node >= Bf) continue;
 #pragma unroll
             for (int p = 0; p < 9; ++p) {
@@ -745,9 +764,6 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
             }
           }
       }
-      float c[11];
-#pragma unroll
-      for (int i = 0; i < 11; ++i) c[i] = a.RCm[(ec * 4 + f) * 12 + i];
 #pragma unroll
       for (int t = 0; t < FT; ++t)
 #pragma unroll
@@ -1160,6 +1176,15 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   a.RCm = rcm;
   a.RCp = rcp;
   a.pinv = pinv;
+  {
+    std::vector<int32_t> mh(M.E, 0);
+    for (int64_t e = 0; e < M.E; ++e)
+      for (int f = 0; f < 4; ++f) mh[e] |= ((M.mode[e * 4 + f] & 3) | (M.hperm[e * 4 + f] & 7) << 2) << (8 * f);
+    int32_t* dm;
+    st = upload(owned, bytes, &dm, mh);
+    if (st != hipSuccess) return st;
+    a.mh4 = dm;
+  }
   {
     int32_t *ds, *fl, *hl;
     st = upload(owned, bytes, &ds, M.dslot);

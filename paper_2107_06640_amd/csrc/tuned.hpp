@@ -21,6 +21,7 @@ struct TArgs {
   const int32_t* tgt;   // [E][4]
   const int8_t* mode;   // [E][4]
   const int8_t* hperm;  // [E][4]
+  const int32_t* mh4;   // [E]: byte f = mode | hperm << 2 of face f
   const int32_t* pinv;  // [6][Bf]
   const int32_t* dslot; // [E] slot of the stored time derivatives, -1 none
   float* gD;            // [slots][N+1][B][9] time derivatives (gravity faces, then hand-over to finer neighbours)
