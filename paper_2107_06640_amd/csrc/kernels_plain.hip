@@ -53,6 +53,7 @@ __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, 
       const int dd = i / (nout * 9), m = (i / 9) % nout, r = i % 9;
       const T* Kd = d.K + (size_t)dd * B * B;
       T acc = T(0);
+#pragma unroll 8
       for (int l = 0; l < nin; ++l) acc += Kd[l * B + m] * sD[l * 9 + r];
       sY[(dd * B + m) * 9 + r] = acc;
     }
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, 
     const int f = i / (Bf * 9), m = (i / 9) % Bf, p = i % 9;
     const T* Em = d.Ef + ((size_t)f * Bf + m) * B;
     T a = T(0), b = T(0);
+#pragma unroll 8
     for (int l = 0; l < B; ++l) {
       a += Em[l] * sI[l * 9 + p];
       b += Em[l] * sIh[l * 9 + p];
@@ -132,10 +134,12 @@ __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, 
     T acc = T(0);
     for (int dd = 0; dd < 3; ++dd) {
       const T* Kd = d.K + ((size_t)dd * B + kk) * B;
+#pragma unroll 8
       for (int l = 0; l < B1; ++l) acc += Kd[l] * sY[(dd * B + l) * 9 + p];
     }
     for (int f = 0; f < 4; ++f) {
       const T* L = d.Lf + ((size_t)f * B + kk) * Bf;
+#pragma unroll 8
       for (int m = 0; m < Bf; ++m) acc -= L[m] * sVh[(f * Bf + m) * 9 + p];
     }
     d.Q[qidx(e, kk, p, RT)] += acc;
@@ -168,6 +172,7 @@ __global__ __launch_bounds__(NT) void k_correct_plain(DevData<T> d, int64_t e0, 
     T acc = T(0);
     for (int f = 0; f < 4; ++f) {
       const T* L = d.Lf + ((size_t)f * B + kk) * Bf;
+#pragma unroll 8
       for (int m = 0; m < Bf; ++m) acc += L[m] * sW[(f * Bf + m) * 9 + p];
     }
     d.Q[qidx(e, kk, p, RT)] -= acc;
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(NT) void k_correct_plain(DevData<T> d, int64_t e0, 
 // the time-integrated boundary flux (stress rows -lambda (eta1 - eta0),
 // velocity rows g H n) lifted with the face rule.
 template <typename T, int N>
-__global__ __launch_bounds__(64) void k_gravity(DevData<T> d, const int32_t* glist) {
+__global__ __launch_bounds__(256) void k_gravity(DevData<T> d, const int32_t* glist) {
   constexpr int B = nbasis(N);
   constexpr int RT = row_tiles(B);
   constexpr int nq = (N + 1) * (N + 1);
@@ -191,25 +196,36 @@ __global__ __launch_bounds__(64) void k_gravity(DevData<T> d, const int32_t* gli
   const double* par = d.g_par + gf * 8;
   const double scale = par[0], nx = par[1], ny = par[2], nz = par[3], Z = par[4], a = par[5], lam = par[6],
                dt = par[7];
+  __shared__ T sD[(N + 1) * B * 9];
+  __shared__ double sFm[nq][N + 1];
   __shared__ double sF[nq][2];
+  // the element's scaled time derivatives, staged once (coalesced)
   const T* D = d.gD + (int64_t)gf * (N + 1) * B * 9;
-  for (int q = tid; q < nq; q += 64) {
+  for (int i = tid; i < (N + 1) * B * 9; i += 256) sD[i] = D[i];
+  __syncthreads();
+  // trace of each derivative at each surface point: one (point, order) pair per thread
+  for (int w = tid; w < nq * (N + 1); w += 256) {
+    const int q = w / (N + 1), m = w % (N + 1);
     const double* Eq = d.Eg + ((size_t)face * nq + q) * B;
-    double Fm[N + 1];
-    for (int m = 0; m <= N; ++m) {
-      double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-      for (int l = 0; l < B; ++l)
-        for (int p = 0; p < 9; ++p) v[p] += Eq[l] * (double)D[(m * B + l) * 9 + p];
-      const double tx = v[0] * nx + v[3] * ny + v[5] * nz;
-      const double ty = v[3] * nx + v[1] * ny + v[4] * nz;
-      const double tz = v[5] * nx + v[4] * ny + v[2] * nz;
-      const double pm = -(tx * nx + ty * ny + tz * nz);
-      Fm[m] = v[6] * nx + v[7] * ny + v[8] * nz + pm / Z;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 8
+    for (int l = 0; l < B; ++l) {
+      const double el = Eq[l];
+#pragma unroll
+      for (int p = 0; p < 9; ++p) v[p] += el * (double)sD[(m * B + l) * 9 + p];
     }
+    const double tx = v[0] * nx + v[3] * ny + v[5] * nz;
+    const double ty = v[3] * nx + v[1] * ny + v[4] * nz;
+    const double tz = v[5] * nx + v[4] * ny + v[2] * nz;
+    const double pm = -(tx * nx + ty * ny + tz * nz);
+    sFm[q][m] = v[6] * nx + v[7] * ny + v[8] * nz + pm / Z;
+  }
+  __syncthreads();
+  for (int q = tid; q < nq; q += 256) {
     const double eta0 = d.eta[(int64_t)gf * nq + q];
     double em = eta0, eta1 = eta0, H = eta0 * dt;
     for (int m = 0; m < N + 24; ++m) {
-      const double fm = m <= N ? Fm[m] : 0.0;
+      const double fm = m <= N ? sFm[q][m] : 0.0;
       em = dt / (m + 1) * (fm - a * em);
       eta1 += em;
       H += em * dt / (m + 2);
@@ -219,17 +235,19 @@ __global__ __launch_bounds__(64) void k_gravity(DevData<T> d, const int32_t* gli
     sF[q][1] = d.g * H;
   }
   __syncthreads();
+  // lift: rows of the three normal stresses (p < 3) and the velocities (p >= 6)
   const double nrm[3] = {nx, ny, nz};
-  for (int i = tid; i < B * 9; i += 64) {
-    const int kk = i / 9, p = i % 9;
+  for (int i = tid; i < B * 6; i += 256) {
+    const int kk = i / 6, j = i % 6;
+    const int p = j < 3 ? j : j + 3;
     const double* Lq = d.Lg + ((size_t)face * B + kk) * nq;
     double acc = 0.0;
     if (p < 3) {
+#pragma unroll 8
       for (int q = 0; q < nq; ++q) acc += Lq[q] * sF[q][0];
-    } else if (p >= 6) {
-      for (int q = 0; q < nq; ++q) acc += Lq[q] * sF[q][1] * nrm[p - 6];
     } else {
-      continue;
+#pragma unroll 8
+      for (int q = 0; q < nq; ++q) acc += Lq[q] * sF[q][1] * nrm[p - 6];
     }
     d.Q[qidx(e, kk, p, RT)] -= (T)(scale * acc);
   }
@@ -250,7 +268,7 @@ hipError_t corr_n(const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipSt
 template <typename T, int N>
 hipError_t grav_n(const DevData<T>& d, const int32_t* glist, int64_t ng, hipStream_t s) {
   if (ng <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_gravity<T, N>), dim3((unsigned)ng), dim3(64), 0, s, d, glist);
+  hipLaunchKernelGGL((k_gravity<T, N>), dim3((unsigned)ng), dim3(256), 0, s, d, glist);
   return hipGetLastError();
 }
 
