@@ -853,9 +853,10 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
         float c[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) c[i] = a.RCp[(ec * 4 + f) * 12 + i];
-        float V[FT][4][9];
+        // one node tile at a time: its Riemann fluxes, then its K rows of the lift
 #pragma unroll
-        for (int t = 0; t < FT; ++t)
+        for (int t = 0; t < FT; ++t) {
+          float V[4][9];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             float in[9], out[9];
@@ -864,14 +865,15 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
             node_flux(c, lam, mu, rinv, in, out);
             const bool ok = 16 * t + 4 * g + v < Bf;
 #pragma unroll
-            for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? -out[p] : 0.0f;
+            for (int p = 0; p < 9; ++p) V[v][p] = ok ? -out[p] : 0.0f;
           }
-        const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL + t0 * 16 * L::ldL);
-        contract_fn<Op, View<R, L::ldL, false>, FT, MH>(dq, AL, Bf, el, g,
-                                                        [&](int t, int v, float (&b)[9]) {
+          const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL + t0 * 16 * L::ldL + 16 * t);
+          contract_fn<Op, View<R, L::ldL, false>, 1, MH>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
+                                                         [&](int, int v, float (&b)[9]) {
 #pragma unroll
-                                                          for (int p = 0; p < 9; ++p) b[p] = V[t][v][p];
-                                                        });
+                                                           for (int p = 0; p < 9; ++p) b[p] = V[v][p];
+                                                         });
+        }
 #if SEIS_FACE_BARRIER
         __builtin_amdgcn_sched_barrier(0);
 #endif
