@@ -600,17 +600,21 @@ __device__ __forceinline__ int64_t logical_block(int remap) {
   return x < r ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
 }
 
-// The predictor keeps I~ in an LDS slice per wavefront, in BF16, when the
-// operands are BF16 (the products round it to BF16 anyway) and the slices fit
-// beside the reference block; otherwise I~ is parked in HBM.
-// The node permutation table (6 x Bf entries) follows.
+// The predictor keeps I~ in an LDS slice per wavefront: all of it, in BF16,
+// when the operands are BF16 (the products round it to BF16 anyway) and the
+// slices fit beside the reference block; in FP32, as many leading row tiles
+// as fit (the rest is parked in HBM). The node permutation table (6 x Bf
+// entries) follows.
 template <class Op, int N, int W>
 struct PredLds {
   using L = Lay<Op, N>;
   static constexpr int slice = L::RT * 36 * 64;  // BF16 values per wavefront
   static constexpr int perm_bytes = (6 * L::Bf * 4 + 15) / 16 * 16;
-  static constexpr bool park_lds = L::BF && L::bytes + W * slice * 2 + perm_bytes <= 160 * 1024;
-  static constexpr int perm_off = L::bytes + (park_lds ? W * slice * 2 : 0);
+  static constexpr int budget = 160 * 1024 - L::bytes - perm_bytes;
+  static constexpr bool park_lds = L::BF && W * slice * 2 <= budget;
+  static constexpr int f32_fit = budget / (W * 36 * 64 * 4);
+  static constexpr int f32_tiles = L::BF ? 0 : (f32_fit < L::RT ? (f32_fit > 0 ? f32_fit : 0) : L::RT);
+  static constexpr int perm_off = L::bytes + (park_lds ? W * slice * 2 : W * f32_tiles * 36 * 64 * 4);
   static constexpr int bytes = perm_off + perm_bytes;
 };
 
@@ -654,7 +658,9 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     float* Ig = a.Ib + grp * (int64_t)(RT * 36 * 64);
     // I~ parked in this wavefront's LDS slice (BF16) or in HBM (see PredLds)
     constexpr bool LP = PredLds<Op, N, W>::park_lds;
+    constexpr int TF = PredLds<Op, N, W>::f32_tiles;  // FP32: leading row tiles of I~ kept in LDS
     unsigned short* ilds = reinterpret_cast<unsigned short*>(lds_raw + L::bytes) + w * PredLds<Op, N, W>::slice;
+    float* flds = reinterpret_cast<float*>(lds_raw + L::bytes) + w * (TF * 36 * 64);
     {
       float J[RT1][4][9];
       CK<Op, N>::run(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
@@ -674,6 +680,8 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
             if (t < RT1) y += J[t < RT1 ? t : 0][v][p];
             if constexpr (LP)
               ilds[((t * 4 + v) * 9 + p) * 64 + lane] = f2bf_dev(y);
+            else if (t < TF)
+              flds[((t * 4 + v) * 9 + p) * 64 + lane] = y;
             else
               ib.st((t * 4 + v) * 9 + p, y);
           }
@@ -691,11 +699,14 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
     // reads are not merged across contractions and kept live)
     auto itil_at = [&](const float* ip) {
       const GroupBuf ib(ip, RT * 36 * 256, lane);
+      const float* fl = flds + opaque_zero();
       return [=](int t, int v, float (&b)[9]) {
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
           if constexpr (LP)
             b[p] = __uint_as_float((unsigned)ilds[((t * 4 + v) * 9 + p) * 64 + lane] << 16);
+          else if (t < TF)
+            b[p] = fl[((t * 4 + v) * 9 + p) * 64 + lane];
           else
             b[p] = ib.ld((t * 4 + v) * 9 + p);
         }
