@@ -207,9 +207,6 @@ __device__ __forceinline__ void mma_slice(f4& acc, const V& A, int i, int k, flo
 #ifndef SEIS_PREFETCH
 #define SEIS_PREFETCH 2  // rows requested ahead by the pipelined contractions
 #endif
-#ifndef SEIS_NT_STORE
-#define SEIS_NT_STORE 0
-#endif
 
 // acc[mt][p] += sum_k A(16 mt + el, k) X[k][p]; X rows produced by rowfn(t, v, b[9])
 // for the input rows k < nrows (rows 16t + 4g + v of this lane). With PIPE the
@@ -768,20 +765,20 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
             const int node = 16 * t + 4 * g + v;
             const int mr = perm[h * Bf + (node < Bf ? node : Bf - 1)];
             if (!send || node >= Bf) continue;
+            float* blk = a.In + in_block(tg >> 2, tg & 3, mr, FT) * 576;
+            const int l = in_lane(tg >> 2, mr);
+            if (half && parity) {
+              // second step of the pair: add to the first half (one writer per
+              // slot; a no-return atomic keeps the load out of this kernel)
 #pragma unroll
-            for (int p = 0; p < 9; ++p) {
-              float* dst = a.In + inidx(tg >> 2, tg & 3, mr, p, FT);
-              if (half && parity) {
-                // second step of the pair: add to the first half (one writer per
-                // slot; a no-return atomic keeps the load out of this kernel)
-                atomicAdd(dst, 0.5f * V[t][v][p]);
-              } else {
-#if SEIS_NT_STORE
-                __builtin_nontemporal_store(half ? 0.5f * V[t][v][p] : V[t][v][p], dst);
-#else
-                *dst = half ? 0.5f * V[t][v][p] : V[t][v][p];
-#endif
-              }
+              for (int p = 0; p < 8; ++p) atomicAdd(blk + 8 * l + p, 0.5f * V[t][v][p]);
+              atomicAdd(blk + 512 + l, 0.5f * V[t][v][8]);
+            } else {
+              const float s = half ? 0.5f : 1.0f;
+              f4* d8 = reinterpret_cast<f4*>(blk + 8 * l);
+              d8[0] = f4{s * V[t][v][0], s * V[t][v][1], s * V[t][v][2], s * V[t][v][3]};
+              d8[1] = f4{s * V[t][v][4], s * V[t][v][5], s * V[t][v][6], s * V[t][v][7]};
+              blk[512 + l] = s * V[t][v][8];
             }
           }
       }
@@ -870,7 +867,7 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
         for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const GroupBuf ib(a.In + ((grp * 4 + f) * (int64_t)(FT * 36 * 64)), FT * 36 * 256, lane);
+        const float* inb = a.In + (grp * 4 + f) * (int64_t)(FT * 4 * 576);
         float c[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) c[i] = a.RCp[(ec * 4 + f) * 12 + i];
@@ -881,8 +878,15 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             float in[9], out[9];
+            const float* blk = inb + (t * 4 + v) * 576;
+            const f4 i0 = reinterpret_cast<const f4*>(blk + 8 * lane)[0];
+            const f4 i1 = reinterpret_cast<const f4*>(blk + 8 * lane)[1];
 #pragma unroll
-            for (int p = 0; p < 9; ++p) in[p] = ib.ld((t * 4 + v) * 9 + p);
+            for (int p = 0; p < 4; ++p) {
+              in[p] = i0[p];
+              in[4 + p] = i1[p];
+            }
+            in[8] = blk[512 + lane];
             node_flux(c, lam, mu, rinv, in, out);
             const bool ok = 16 * t + 4 * g + v < Bf;
 #pragma unroll
