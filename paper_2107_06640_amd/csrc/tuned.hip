@@ -809,18 +809,28 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 
     {
       // Q += dq for live elements and rows below B
+      // QB row tiles are requested before the first of their stores (raw
+      // buffer accesses may alias, so a store orders later loads behind it):
+      // one memory latency per QB tiles. All four tiles at order 6 in BF16;
+      // two where registers are tighter.
+      constexpr int QB = (L::BF && RT <= 4) ? RT : 2;
       const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
 #pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        float q[36];  // the whole row tile before its stores (see the park above)
+      for (int t0 = 0; t0 < RT; t0 += QB) {
+        float q[QB][36];
 #pragma unroll
-        for (int r = 0; r < 36; ++r) q[r] = qb.ld(t * 36 + r);
+        for (int u = 0; u < QB; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (!live || 16 * t + 4 * g + v >= B) continue;
+          for (int r = 0; r < 36; ++r) q[u][r] = t0 + u < RT ? qb.ld((t0 + u) * 36 + r) : 0.0f;
 #pragma unroll
-          for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[v * 9 + p] + dq[t][p][v]);
-        }
+        for (int u = 0; u < QB; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int t = t0 + u;
+            if (t >= RT || !live || 16 * t + 4 * g + v >= B) continue;
+#pragma unroll
+            for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[u][v * 9 + p] + dq[t < RT ? t : 0][p][v]);
+          }
       }
     }
   }
