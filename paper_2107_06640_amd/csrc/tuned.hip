@@ -913,20 +913,27 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
         __builtin_amdgcn_sched_barrier(0);
 #endif
       }
+      // up to four of the pass's row tiles are requested before their stores
+      // (raw buffer accesses may alias): one memory latency per batch
+      constexpr int QB = MH < 4 ? MH : 4;
       const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
 #pragma unroll
-      for (int tt = 0; tt < MH; ++tt) {
-        const int t = t0 + tt;
-        if (t >= RT) continue;
-        float q[36];  // the whole row tile before its stores (raw buffer accesses may alias)
+      for (int u0 = 0; u0 < MH; u0 += QB) {
+        float q[QB][36];
 #pragma unroll
-        for (int r = 0; r < 36; ++r) q[r] = qb.ld(t * 36 + r);
+        for (int u = 0; u < QB; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (!live || 16 * t + 4 * g + v >= B) continue;
+          for (int r = 0; r < 36; ++r)
+            q[u][r] = (u0 + u < MH && t0 + u0 + u < RT) ? qb.ld((t0 + u0 + u) * 36 + r) : 0.0f;
 #pragma unroll
-          for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[v * 9 + p] + dq[tt][p][v]);
-        }
+        for (int u = 0; u < QB; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int uu = u0 + u, t = t0 + uu;
+            if (uu >= MH || t >= RT || !live || 16 * t + 4 * g + v >= B) continue;
+#pragma unroll
+            for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[u][v * 9 + p] + dq[uu < MH ? uu : 0][p][v]);
+          }
       }
     }
   }
