@@ -839,6 +839,9 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #ifndef SEIS_FACE_BARRIER
 #define SEIS_FACE_BARRIER 1
 #endif
+#ifndef SEIS_CORR_AHEAD
+#define SEIS_CORR_AHEAD 1  // corrector: (face, node tile) steps whose inbox traces are requested ahead
+#endif
 
 // Corrector: Q -= sum_f L_f flux(neighbour trace of face f). The output rows
 // are produced in SPLIT passes (the face fluxes are recomputed per
@@ -850,6 +853,7 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
   constexpr int B = L::B, Bf = L::Bf, RT = L::RT, FT = L::FT;
   constexpr int NS = (SPLIT > RT) ? RT : SPLIT;
   constexpr int MH = (RT + NS - 1) / NS;  // row tiles per pass
+  constexpr int CD = SEIS_CORR_AHEAD;       // inbox steps requested ahead
   using R = RefT<Op>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const R* lds = reinterpret_cast<const R*>(lds_raw);
@@ -875,43 +879,57 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
       for (int t = 0; t < MH; ++t)
 #pragma unroll
         for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
+      // the (face, node tile) steps are software-pipelined: the inbox traces
+      // of step s + CD are requested while step s computes its Riemann fluxes
+      // and its rows of the lift (one scheduling region per step, so the
+      // requests are not sunk to their use)
+      constexpr int NSTEP = 4 * FT;
+      const float* inb = a.In + grp * 4 * (int64_t)(FT * 4 * 576);
+      auto load_step = [&](int s, float(&dst)[4][9]) {
+        const float* blk0 = inb + s * (4 * 576);  // face s / FT, tile s % FT
 #pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const float* inb = a.In + (grp * 4 + f) * (int64_t)(FT * 4 * 576);
-        float c[11];
+        for (int v = 0; v < 4; ++v) {
+          const float* blk = blk0 + v * 576;
+          const f4 i0 = reinterpret_cast<const f4*>(blk + 8 * lane)[0];
+          const f4 i1 = reinterpret_cast<const f4*>(blk + 8 * lane)[1];
 #pragma unroll
-        for (int i = 0; i < 11; ++i) c[i] = a.RCp[(ec * 4 + f) * 12 + i];
-        // one node tile at a time: its Riemann fluxes, then its K rows of the lift
-#pragma unroll
-        for (int t = 0; t < FT; ++t) {
-          float V[4][9];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            float in[9], out[9];
-            const float* blk = inb + (t * 4 + v) * 576;
-            const f4 i0 = reinterpret_cast<const f4*>(blk + 8 * lane)[0];
-            const f4 i1 = reinterpret_cast<const f4*>(blk + 8 * lane)[1];
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-              in[p] = i0[p];
-              in[4 + p] = i1[p];
-            }
-            in[8] = blk[512 + lane];
-            node_flux(c, lam, mu, rinv, in, out);
-            const bool ok = 16 * t + 4 * g + v < Bf;
-#pragma unroll
-            for (int p = 0; p < 9; ++p) V[v][p] = ok ? -out[p] : 0.0f;
+          for (int p = 0; p < 4; ++p) {
+            dst[v][p] = i0[p];
+            dst[v][4 + p] = i1[p];
           }
-          const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL + t0 * 16 * L::ldL + 16 * t);
-          contract_fn<Op, View<R, L::ldL, false>, 1, MH>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
-                                                         [&](int, int v, float (&b)[9]) {
-#pragma unroll
-                                                           for (int p = 0; p < 9; ++p) b[p] = V[v][p];
-                                                         });
+          dst[v][8] = blk[512 + lane];
         }
-#if SEIS_FACE_BARRIER
+      };
+      float c[4][11];
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int i = 0; i < 11; ++i) c[f][i] = a.RCp[(ec * 4 + f) * 12 + i];
+      float tb[CD + 1][4][9];
+#pragma unroll
+      for (int s = 0; s < CD; ++s) load_step(s, tb[s]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int s = 0; s < NSTEP; ++s) {
+        const int f = s / FT, t = s % FT;
+        if (s + CD < NSTEP) load_step(s + CD, tb[(s + CD) % (CD + 1)]);
+        float(&cur)[4][9] = tb[s % (CD + 1)];
+        float V[4][9];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float out[9];
+          node_flux(c[f], lam, mu, rinv, cur[v], out);
+          const bool ok = 16 * t + 4 * g + v < Bf;
+#pragma unroll
+          for (int p = 0; p < 9; ++p) V[v][p] = ok ? -out[p] : 0.0f;
+        }
+        const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL + t0 * 16 * L::ldL + 16 * t);
+        contract_fn<Op, View<R, L::ldL, false>, 1, MH>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
+                                                       [&](int, int v, float (&b)[9]) {
+#pragma unroll
+                                                         for (int p = 0; p < 9; ++p) b[p] = V[v][p];
+                                                       });
         __builtin_amdgcn_sched_barrier(0);
-#endif
       }
       // up to four of the pass's row tiles are requested before their stores
       // (raw buffer accesses may alias): one memory latency per batch
