@@ -344,29 +344,49 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
       for (int mt = 0; mt < RTO; ++mt)
         dst[mt] = d == 0 ? A0.at(16 * mt + el, k) : (d == 1 ? A1.at(16 * mt + el, k) : A2.at(16 * mt + el, k));
     };
-    // software pipeline over the slabs: while the products of slab s run, the
-    // K^d fragments of slab s+1 are read from LDS and its star product is
-    // formed (one scheduling region per slab, so neither is sunk to its use)
-    auto star_of = [&](int s, float(&z)[9]) {
-      const int d = s / NV, i = s % NV;
-      apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[i >> 2][i & 3], z);
-    };
-    float zb[2][9];
-    load_a(0, an[0]);
-    star_of(0, zb[0]);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int s = 0; s < 3 * NV; ++s) {
-      if (s + 1 < 3 * NV) load_a(s + 1, an[(s + 1) & 1]);
-#pragma unroll
-      for (int mt = 0; mt < RTO; ++mt) {
-        const float af = an[s & 1][mt];
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-          acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, zb[s & 1][P0 + p], acc[mt][p], 0, 0, 0);
-      }
-      if (s + 1 < 3 * NV) star_of(s + 1, zb[(s + 1) & 1]);
+    if constexpr (N <= 5) {
+      // software pipeline over the slabs: while the products of slab s run,
+      // the K^d fragments of slab s+1 are read from LDS and its star product
+      // is formed (one scheduling region per slab, so neither is sunk to its
+      // use). At N = 6 the second star buffer spills; that order keeps the
+      // plain loop.
+      auto star_of = [&](int s, float(&z)[9]) {
+        const int d = s / NV, i = s % NV;
+        apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[i >> 2][i & 3], z);
+      };
+      float zb[2][9];
+      load_a(0, an[0]);
+      star_of(0, zb[0]);
       __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int s = 0; s < 3 * NV; ++s) {
+        if (s + 1 < 3 * NV) load_a(s + 1, an[(s + 1) & 1]);
+#pragma unroll
+        for (int mt = 0; mt < RTO; ++mt) {
+          const float af = an[s & 1][mt];
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+            acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, zb[s & 1][P0 + p], acc[mt][p], 0, 0, 0);
+        }
+        if (s + 1 < 3 * NV) star_of(s + 1, zb[(s + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+      load_a(0, an[0]);
+#pragma unroll
+      for (int s = 0; s < 3 * NV; ++s) {
+        const int d = s / NV, i = s % NV, t = i >> 2, v = i & 3;
+        if (s + 1 < 3 * NV) load_a(s + 1, an[(s + 1) & 1]);
+        float z[9];
+        apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z);
+#pragma unroll
+        for (int mt = 0; mt < RTO; ++mt) {
+          const float af = an[s & 1][mt];
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+            acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, z[P0 + p], acc[mt][p], 0, 0, 0);
+        }
+      }
     }
   } else {
 #pragma unroll
