@@ -19,9 +19,11 @@ namespace seis {
 
 namespace {
 
-constexpr int NT = 256;
+// Threads per element: 256 for throughput; a launch over a few elements (a
+// tiny LTS cluster) is bound by the latency of one work-group, so it uses 1024.
+constexpr int NT_WIDE = 256, NT_TALL = 1024, TALL_BELOW = 256;
 
-template <typename T, int N>
+template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, int parity) {
   constexpr int B = nbasis(N), Bf = nface(N);
   constexpr int B1 = nbasis(N - 1);
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, 
   }
 }
 
-template <typename T, int N>
+template <typename T, int N, int NT>
 __global__ __launch_bounds__(NT) void k_correct_plain(DevData<T> d, int64_t e0, int parity) {
   constexpr int B = nbasis(N), Bf = nface(N);
   constexpr int RT = row_tiles(B), FT = row_tiles(Bf);
@@ -256,13 +258,19 @@ __global__ __launch_bounds__(256) void k_gravity(DevData<T> d, const int32_t* gl
 template <typename T, int N>
 hipError_t pred_n(const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipStream_t s) {
   if (ne <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_predict_plain<T, N>), dim3((unsigned)ne), dim3(NT), 0, s, d, e0, parity);
+  if (ne < TALL_BELOW)
+    hipLaunchKernelGGL((k_predict_plain<T, N, NT_TALL>), dim3((unsigned)ne), dim3(NT_TALL), 0, s, d, e0, parity);
+  else
+    hipLaunchKernelGGL((k_predict_plain<T, N, NT_WIDE>), dim3((unsigned)ne), dim3(NT_WIDE), 0, s, d, e0, parity);
   return hipGetLastError();
 }
 template <typename T, int N>
 hipError_t corr_n(const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipStream_t s) {
   if (ne <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_correct_plain<T, N>), dim3((unsigned)ne), dim3(NT), 0, s, d, e0, parity);
+  if (ne < TALL_BELOW)
+    hipLaunchKernelGGL((k_correct_plain<T, N, NT_TALL>), dim3((unsigned)ne), dim3(NT_TALL), 0, s, d, e0, parity);
+  else
+    hipLaunchKernelGGL((k_correct_plain<T, N, NT_WIDE>), dim3((unsigned)ne), dim3(NT_WIDE), 0, s, d, e0, parity);
   return hipGetLastError();
 }
 template <typename T, int N>
