@@ -25,17 +25,19 @@ __host__ __device__ inline int64_t qidx(int64_t e, int r, int p, int RT) {
   return (((grp * RT + t) * 4 + v) * 9 + p) * 64 + el + 16 * g;
 }
 
-// In[e][f][m][p] with FT node tiles per face. The face nodes follow the same
-// (tile, slot, lane) order, but the nine quantities of one node sit together:
-// per (group, face, tile, slot) a block of 576 values, the quantities 0..7 of
-// lane l at 8l..8l+7 (two aligned 16-byte vectors) and quantity 8 at 512 + l.
-// A writer then hands over one node with three stores instead of nine, and a
+// In[e][f][m][p] with FT node tiles per face. Node m of a face sits in tile
+// m >> 4, register v = (m >> 2) & 3 and lane group g = m & 3 (the transpose of
+// the row order of Q inside a tile, so that a partial last tile fills whole
+// register slots first). The nine quantities of one node sit together: per
+// (group, face, tile, v) a block of 576 values, the quantities 0..7 of lane l
+// at 8l..8l+7 (two aligned 16-byte vectors) and quantity 8 at 512 + l. A
+// writer then hands over one node with three stores instead of nine, and a
 // reader gets it with three loads.
 __host__ __device__ inline int64_t in_block(int64_t e, int f, int m, int FT) {
-  const int t = m >> 4, v = m & 3;
+  const int t = m >> 4, v = (m >> 2) & 3;
   return (((e >> 4) * 4 + f) * FT + t) * 4 + v;
 }
-__host__ __device__ inline int in_lane(int64_t e, int m) { return int(e & 15) + 16 * ((m >> 2) & 3); }
+__host__ __device__ inline int in_lane(int64_t e, int m) { return int(e & 15) + 16 * (m & 3); }
 __host__ __device__ inline int64_t inidx(int64_t e, int f, int m, int p, int FT) {
   const int l = in_lane(e, m);
   return in_block(e, f, m, FT) * 576 + (p < 8 ? 8 * l + p : 512 + l);

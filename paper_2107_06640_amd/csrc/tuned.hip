@@ -131,6 +131,12 @@ __device__ __forceinline__ void node_flux(const float* c, float lam, float mu, f
 template <class Op>
 using RefT = typename std::conditional<std::is_same<Op, OpF32>::value, float, unsigned short>::type;
 
+// Face node held in slot c = 16t + 4g + v of a node tile (lane group g,
+// register v): node 16t + 4v + g. The 4 x 4 (g, v) grid of a tile is
+// transposed so that the nodes of a partial last tile fill whole K slabs (v)
+// of the FP32 products first. The map is its own inverse.
+__host__ __device__ constexpr int node_of(int c) { return (c & ~15) + 4 * (c & 3) + ((c >> 2) & 3); }
+
 template <class Op, int N>
 struct Lay {
   static constexpr bool BF = std::is_same<Op, OpBF16>::value;
@@ -139,11 +145,12 @@ struct Lay {
   static constexpr int r4(int x) { return BF ? (x + 3) / 4 * 4 : x; }
   static constexpr int ldK = r4(B1);   // K^d[l < B][m < B1]   (volume: A(k,l) = K[k][l]; FP32 CK: A(m,l) = K[l][m])
   static constexpr int ldT = r4(B);    // BF16 CK: (K^d)^T[m < B1][l < B]
-  static constexpr int ldE = r4(B);    // E_f[node < Bf][row < B]
-  static constexpr int ldL = r4(Bf);   // L_f[row < B][node < Bf]
+  // face nodes in slot order (see node_of): FT * 16 slots per face
+  static constexpr int ldE = r4(B);       // E_f[slot < 16 FT][row < B]
+  static constexpr int ldL = 16 * FT;     // L_f[row < B][slot < 16 FT]
   static constexpr int nK = 3 * B * ldK;
   static constexpr int nT = BF ? 3 * B1 * ldT : 0;
-  static constexpr int nE = 4 * Bf * ldE;
+  static constexpr int nE = 4 * 16 * FT * ldE;
   static constexpr int nL = 4 * B * ldL;
   static constexpr int maxld = (ldK > ldE ? ldK : ldE) > ldL ? (ldK > ldE ? ldK : ldE) : ldL;
   static constexpr int tail = 16 * (maxld > ldT ? maxld : ldT) + 64;
@@ -214,13 +221,18 @@ __device__ __forceinline__ void mma_slice(f4& acc, const V& A, int i, int k, flo
 // before the products of the current one, and a scheduling barrier per row
 // keeps the compiler from hoisting every load of the loop (which would need a
 // register per load in flight).
-template <class Op, class V, int NT, int MT, bool PIPE = false, class RowFn>
+// NODEK: the K index runs over face nodes in slot order (node 16t + 4v + g in
+// slot (t, g, v)), so a slab (t, v) holds nodes 16t + 4v .. 16t + 4v + 3 and a
+// partial last tile needs only its first slabs.
+template <class Op, class V, int NT, int MT, bool PIPE = false, bool NODEK = false, class RowFn>
 __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nrows, int el, int g, RowFn rowfn) {
   if constexpr (std::is_same<Op, OpF32>::value) {
     constexpr int D = PIPE ? SEIS_PREFETCH : 0;  // rows requested ahead
     float b[D + 1][9];
     float an[2][MT];  // A fragments of this row and the next (read from LDS one row ahead)
-    auto valid = [&](int i) { return i < 4 * NT && 16 * (i >> 2) + (i & 3) < nrows; };
+    auto valid = [&](int i) {
+      return i < 4 * NT && 16 * (i >> 2) + (NODEK ? 4 * (i & 3) : (i & 3)) < nrows;
+    };
     auto load_a = [&](int i, float(&dst)[MT]) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) dst[mt] = A.at(16 * mt + el, 16 * (i >> 2) + 4 * g + (i & 3));
@@ -753,14 +765,14 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
       for (int t = 0; t < FT; ++t)
 #pragma unroll
         for (int p = 0; p < 9; ++p) va[t][p] = f4{0.f, 0.f, 0.f, 0.f};
-      const View<R, L::ldE, false> AE(lds + L::oE + f * Bf * L::ldE);
+      const View<R, L::ldE, false> AE(lds + L::oE + f * 16 * FT * L::ldE);
       contract_fn<Op, View<R, L::ldE, false>, RT, FT, true>(va, AE, B, el, g, itil_at(Ig));
       float V[FT][4][9];
 #pragma unroll
       for (int t = 0; t < FT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const bool ok = 16 * t + 4 * g + v < Bf;
+          const bool ok = 16 * t + 4 * v + g < Bf;  // node in slot (t, g, v)
 #pragma unroll
           for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? va[t][p][v] : 0.0f;
         }
@@ -782,7 +794,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
         for (int t = 0; t < FT; ++t)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int node = 16 * t + 4 * g + v;
+            const int node = 16 * t + 4 * v + g;
             const int mr = perm[h * Bf + (node < Bf ? node : Bf - 1)];
             if (!send || node >= Bf) continue;
             float* blk = a.In + in_block(tg >> 2, tg & 3, mr, FT) * 576;
@@ -812,7 +824,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
           for (int p = 0; p < 9; ++p) V[t][v][p] = -out[p];
         }
       const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL);
-      contract_fn<Op, View<R, L::ldL, false>, FT, RT>(dq, AL, Bf, el, g,
+      contract_fn<Op, View<R, L::ldL, false>, FT, RT, false, true>(dq, AL, Bf, el, g,
                                                       [&](int t, int v, float (&b)[9]) {
 #pragma unroll
                                                         for (int p = 0; p < 9; ++p) b[p] = V[t][v][p];
@@ -939,12 +951,12 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
         for (int v = 0; v < 4; ++v) {
           float out[9];
           node_flux(c[f], lam, mu, rinv, cur[v], out);
-          const bool ok = 16 * t + 4 * g + v < Bf;
+          const bool ok = 16 * t + 4 * v + g < Bf;  // node in slot (t, g, v)
 #pragma unroll
           for (int p = 0; p < 9; ++p) V[v][p] = ok ? -out[p] : 0.0f;
         }
         const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL + t0 * 16 * L::ldL + 16 * t);
-        contract_fn<Op, View<R, L::ldL, false>, 1, MH>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
+        contract_fn<Op, View<R, L::ldL, false>, 1, MH, false, true>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
                                                        [&](int, int v, float (&b)[9]) {
 #pragma unroll
                                                          for (int p = 0; p < 9; ++p) b[p] = V[v][p];
@@ -1179,11 +1191,14 @@ std::vector<double> ref_image(const Model& M) {
         if (L::BF) r[L::oT + (d * B1 + l) * L::ldT + k] = v;
       }
   for (int f = 0; f < 4; ++f)
-    for (int m = 0; m < Bf; ++m)
+    for (int c = 0; c < 16 * L::FT; ++c) {
+      const int m = node_of(c);
+      if (m >= Bf) continue;  // padding slot: zero
       for (int k = 0; k < B; ++k) {
-        r[L::oE + (f * Bf + m) * L::ldE + k] = M.ref.E[(f * Bf + m) * B + k];
-        r[L::oL + (f * B + k) * L::ldL + m] = M.ref.L[(f * B + k) * Bf + m];
+        r[L::oE + (f * 16 * L::FT + c) * L::ldE + k] = M.ref.E[(f * Bf + m) * B + k];
+        r[L::oL + (f * B + k) * L::ldL + c] = M.ref.L[(f * B + k) * Bf + m];
       }
+    }
   return r;
 }
 
