@@ -14,17 +14,19 @@ namespace seis {
 // out_p = (sum_e c_e A_e) v for the combination c = (cx, cy, cz).
 template <typename T>
 __device__ __forceinline__ void apply_star(T cx, T cy, T cz, T lam, T mu, T rinv, const T v[9], T out[9]) {
-  const T l2m = lam + T(2) * mu;
+  // the minus signs are carried by the coefficients: negation is exact, so
+  // this equals -(l2m cx vx + ...) etc. bit for bit, without sign flips
+  const T nl2m = -(lam + T(2) * mu), nlam = -lam, nmu = -mu, nr = -rinv;
   const T vx = v[6], vy = v[7], vz = v[8];
-  out[0] = -(l2m * cx * vx + lam * cy * vy + lam * cz * vz);
-  out[1] = -(lam * cx * vx + l2m * cy * vy + lam * cz * vz);
-  out[2] = -(lam * cx * vx + lam * cy * vy + l2m * cz * vz);
-  out[3] = -mu * (cx * vy + cy * vx);
-  out[4] = -mu * (cy * vz + cz * vy);
-  out[5] = -mu * (cx * vz + cz * vx);
-  out[6] = -rinv * (cx * v[0] + cy * v[3] + cz * v[5]);
-  out[7] = -rinv * (cx * v[3] + cy * v[1] + cz * v[4]);
-  out[8] = -rinv * (cx * v[5] + cy * v[4] + cz * v[2]);
+  out[0] = nl2m * cx * vx + nlam * cy * vy + nlam * cz * vz;
+  out[1] = nlam * cx * vx + nl2m * cy * vy + nlam * cz * vz;
+  out[2] = nlam * cx * vx + nlam * cy * vy + nl2m * cz * vz;
+  out[3] = nmu * (cx * vy + cy * vx);
+  out[4] = nmu * (cy * vz + cz * vy);
+  out[5] = nmu * (cx * vz + cz * vx);
+  out[6] = nr * (cx * v[0] + cy * v[3] + cz * v[5]);
+  out[7] = nr * (cx * v[3] + cy * v[1] + cz * v[4]);
+  out[8] = nr * (cx * v[5] + cy * v[4] + cz * v[2]);
 }
 
 // out_p = sum_e (A_e w_e)_p for three vectors w_x, w_y, w_z (physical gradient components).

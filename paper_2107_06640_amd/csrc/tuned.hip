@@ -90,10 +90,10 @@ __device__ __forceinline__ void flux_comp(const float* u, float lam, float mu, f
   if constexpr (p == 8) { ux = -rinv * u[5]; uy = -rinv * u[4]; uz = -rinv * u[2]; }
 }
 
-// Godunov flux A-hat^-(n) q^b at one face node (Sec. 4.2), with the middle
-// state a linear map of the given trace: c = n_x, n_y, n_z, then the eight
-// scaled coefficients of (s_n^b, v_n^b) from (s_n, v_n) and (t_t^b, v_t^b)
-// from (t_t, v_t).
+// Minus the Godunov flux A-hat^-(n) q^b at one face node (Sec. 4.2), with the
+// middle state a linear map of the given trace: c = n_x, n_y, n_z, then the
+// eight scaled coefficients of (s_n^b, v_n^b) from (s_n, v_n) and
+// (t_t^b, v_t^b) from (t_t, v_t).
 __device__ __forceinline__ void node_flux(const float* c, float lam, float mu, float rinv, const float* in,
                                           float* out) {
   const float nx = c[0], ny = c[1], nz = c[2];
@@ -109,15 +109,16 @@ __device__ __forceinline__ void node_flux(const float* c, float lam, float mu, f
   const float tbx = c[7] * ttx + c[8] * vtx, tby = c[7] * tty + c[8] * vty, tbz = c[7] * ttz + c[8] * vtz;
   const float vbx = c[9] * ttx + c[10] * vtx, vby = c[9] * tty + c[10] * vty, vbz = c[9] * ttz + c[10] * vtz;
   const float w = 2.0f * vnb;
-  out[0] = -(lam * vnb + mu * (w * nx * nx + 2.0f * vbx * nx));
-  out[1] = -(lam * vnb + mu * (w * ny * ny + 2.0f * vby * ny));
-  out[2] = -(lam * vnb + mu * (w * nz * nz + 2.0f * vbz * nz));
-  out[3] = -mu * (w * nx * ny + vbx * ny + vby * nx);
-  out[4] = -mu * (w * ny * nz + vby * nz + vbz * ny);
-  out[5] = -mu * (w * nx * nz + vbx * nz + vbz * nx);
-  out[6] = -rinv * (snb * nx + tbx);
-  out[7] = -rinv * (snb * ny + tby);
-  out[8] = -rinv * (snb * nz + tbz);
+  // out is minus the flux (the sign every caller applies), so no sign flips
+  out[0] = lam * vnb + mu * (w * nx * nx + 2.0f * vbx * nx);
+  out[1] = lam * vnb + mu * (w * ny * ny + 2.0f * vby * ny);
+  out[2] = lam * vnb + mu * (w * nz * nz + 2.0f * vbz * nz);
+  out[3] = mu * (w * nx * ny + vbx * ny + vby * nx);
+  out[4] = mu * (w * ny * nz + vby * nz + vbz * ny);
+  out[5] = mu * (w * nx * nz + vbx * nz + vbz * nx);
+  out[6] = rinv * (snb * nx + tbx);
+  out[7] = rinv * (snb * ny + tby);
+  out[8] = rinv * (snb * nz + tbz);
 }
 
 // ---------------------------------------------------------------------------
@@ -821,7 +822,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
           float out[9];
           node_flux(c, lam, mu, rinv, V[t][v], out);
 #pragma unroll
-          for (int p = 0; p < 9; ++p) V[t][v][p] = -out[p];
+          for (int p = 0; p < 9; ++p) V[t][v][p] = out[p];
         }
       const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL);
       contract_fn<Op, View<R, L::ldL, false>, FT, RT, false, true>(dq, AL, Bf, el, g,
@@ -953,7 +954,7 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
           node_flux(c[f], lam, mu, rinv, cur[v], out);
           const bool ok = 16 * t + 4 * v + g < Bf;  // node in slot (t, g, v)
 #pragma unroll
-          for (int p = 0; p < 9; ++p) V[v][p] = ok ? -out[p] : 0.0f;
+          for (int p = 0; p < 9; ++p) V[v][p] = ok ? out[p] : 0.0f;
         }
         const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL + t0 * 16 * L::ldL + 16 * t);
         contract_fn<Op, View<R, L::ldL, false>, 1, MH, false, true>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
