@@ -209,9 +209,6 @@ struct View {
   }
 };
 
-template <class Op, class V>
-__device__ __forceinline__ void mma_slice(f4& acc, const V& A, int i, int k, float b);
-
 #ifndef SEIS_PREFETCH
 #define SEIS_PREFETCH 2  // rows requested ahead by the pipelined contractions
 #endif
@@ -904,8 +901,6 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
     const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
 #pragma unroll
     for (int h = 0; h < NS; ++h) {
-      constexpr int dummy = 0;
-      (void)dummy;
       const int t0 = h * MH;
       f4 dq[MH][9];
 #pragma unroll
