@@ -205,7 +205,7 @@ def test_tuned_fp32_lts():
     assert fe.max() < TOL32
 
 
-@pytest.mark.parametrize("order", [4, 6])
+@pytest.mark.parametrize("order", [3, 4, 5, 6, 7])
 def test_tuned_bf16_coupled_gravity(order):
     mesh, mats = inputs.coupled_box(4, 3, 4, cell=500.0, water_layers=2, jitter=0.15, seed=order)
     o, d, e = run_pair(mesh, mats, order, 2, precision="bf16", kernel="tuned", seed=order)
