@@ -155,9 +155,12 @@ struct Lay {
   static constexpr int nL = 4 * B * ldL;
   static constexpr int maxld = (ldK > ldE ? ldK : ldE) > ldL ? (ldK > ldE ? ldK : ldE) : ldL;
   static constexpr int tail = 16 * (maxld > ldT ? maxld : ldT) + 64;
-  static constexpr int oK = 0, oT = nK, oE = nK + nT, oL = oE + nE;
+  // the lift block starts on a 16-byte boundary (the corrector stages it alone)
+  static constexpr int oK = 0, oT = nK, oE = nK + nT, oL = (oE + nE + 7) / 8 * 8;
   static constexpr int total = oL + nL + tail;
   static constexpr int bytes = (total * (BF ? 2 : 4) + 15) / 16 * 16;
+  // the corrector stages only the lifts and the tail: [oL, total)
+  static constexpr int lift_bytes = ((nL + tail) * (BF ? 2 : 4) + 15) / 16 * 16;
 };
 
 // A zero the compiler cannot see through. Views built with it are re-read
@@ -886,8 +889,10 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
   constexpr int CD = SEIS_CORR_AHEAD;       // inbox steps requested ahead
   using R = RefT<Op>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const R* lds = reinterpret_cast<const R*>(lds_raw);
-  stage_ref<Op>(lds_raw, a.ref, L::bytes, 64 * W);
+  // only the lifts (and the tail their reads may run into) are staged: ldsL
+  // holds the block from offset oL on
+  const R* ldsL = reinterpret_cast<const R*>(lds_raw);
+  stage_ref<Op>(lds_raw, reinterpret_cast<const R*>(a.ref) + L::oL, L::lift_bytes, 64 * W);
   __syncthreads();
   // the wavefront index is uniform across the wavefront: keep it (and every
   // group base and buffer descriptor derived from it) in scalar registers
@@ -951,7 +956,7 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
 #pragma unroll
           for (int p = 0; p < 9; ++p) V[v][p] = ok ? out[p] : 0.0f;
         }
-        const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL + t0 * 16 * L::ldL + 16 * t);
+        const View<R, L::ldL, false> AL(ldsL + f * B * L::ldL + t0 * 16 * L::ldL + 16 * t);
         contract_fn<Op, View<R, L::ldL, false>, 1, MH, false, true>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
                                                        [&](int, int v, float (&b)[9]) {
 #pragma unroll
@@ -1122,9 +1127,10 @@ hipError_t launch_corr(const TArgs& a, int64_t e0, int64_t e1, const LaunchCfg& 
   using L = Lay<Op, N>;
   const int64_t ng = ((e1 - 1) >> 4) - (e0 >> 4) + 1;
   const unsigned grid = grid_size(ng, W, c.cap);
-  static hipError_t attr = prep(k_correct_tuned<Op, N, W, SPLIT>, L::bytes);
+  static hipError_t attr = prep(k_correct_tuned<Op, N, W, SPLIT>, L::lift_bytes);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_correct_tuned<Op, N, W, SPLIT>), dim3(grid), dim3(64 * W), L::bytes, s, a, e0, e1, c.remap);
+  hipLaunchKernelGGL((k_correct_tuned<Op, N, W, SPLIT>), dim3(grid), dim3(64 * W), L::lift_bytes, s, a, e0, e1,
+                     c.remap);
   return hipGetLastError();
 }
 
