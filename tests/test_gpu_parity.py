@@ -66,8 +66,9 @@ def check64(o, d, e, tol=TOL64):
         assert ee <= tol
 
 
-def test_periodic_elastic_order3_fp64():
-    mesh = inputs.cfg1_mesh(3)
+@pytest.mark.parametrize("n", [3, 6])  # 6: the full 6 x 6 x 6-cube periodic elastic cube (1296 tets)
+def test_periodic_elastic_order3_fp64(n):
+    mesh = inputs.cfg1_mesh(n)
     mats = inputs.uniform_materials(mesh, 2700.0, 6000.0, 3464.0)
     o, d, e = run_pair(mesh, mats, 3, 4, cfl=0.5)
     check64(o, d, e)
