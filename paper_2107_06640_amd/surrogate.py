@@ -185,7 +185,7 @@ def main():
     ap.add_argument("--modes", type=int, default=12)
     ap.add_argument("--layers", type=int, default=4)
     ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--out", default="gpurun_out/surrogate")
+    ap.add_argument("--out", default="surrogate_out")
     ap.add_argument("--save-data", action="store_true", help="also write the generated runs (data.npz)")
     args = ap.parse_args()
     import torch
