@@ -28,12 +28,24 @@ FLAGS = [
 ]
 
 
-EXTRA = os.environ.get("SEIS_EXTRA_FLAGS", "").split()
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over every source and header in csrc/.
+
+    Compiled in as SEIS_SOURCE_HASH: the autotuner keys its cache on it, so a
+    launch configuration measured on other kernels is never reused.
+    """
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".cpp", ".hpp")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
-def _compile(src: str) -> str:
+def _compile(src: str, defs: list[str]) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, *EXTRA, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *defs, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -43,8 +55,9 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False, out: str = LIB) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    defs = [f'-DSEIS_SOURCE_HASH="{source_hash()}"']
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, defs), SOURCES))
     tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -39,6 +39,10 @@
 #include "layout.hpp"
 #include "tuned.hpp"
 
+#ifndef SEIS_SOURCE_HASH
+#define SEIS_SOURCE_HASH "unhashed"
+#endif
+
 namespace seis {
 
 namespace {
@@ -166,16 +170,9 @@ struct Lay {
 // A zero the compiler cannot see through. Views built with it are re-read
 // from LDS where they are used, instead of being hoisted into registers for
 // the whole kernel (the reference block is loop-invariant).
-#ifndef SEIS_LAUNDER
-#define SEIS_LAUNDER 1
-#endif
 __device__ __forceinline__ int opaque_zero() {
   int z = 0;
-#if SEIS_LAUNDER == 1
   asm volatile("" : "+s"(z));
-#elif SEIS_LAUNDER == 2
-  asm("" : "+s"(z));
-#endif
   return z;
 }
 
@@ -212,9 +209,8 @@ struct View {
   }
 };
 
-#ifndef SEIS_PREFETCH
-#define SEIS_PREFETCH 2  // rows requested ahead by the pipelined contractions
-#endif
+// rows requested ahead by the pipelined contractions
+constexpr int kPrefetch = 2;
 
 // acc[mt][p] += sum_k A(16 mt + el, k) X[k][p]; X rows produced by rowfn(t, v, b[9])
 // for the input rows k < nrows (rows 16t + 4g + v of this lane). With PIPE the
@@ -228,7 +224,7 @@ struct View {
 template <class Op, class V, int NT, int MT, bool PIPE = false, bool NODEK = false, class RowFn>
 __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nrows, int el, int g, RowFn rowfn) {
   if constexpr (std::is_same<Op, OpF32>::value) {
-    constexpr int D = PIPE ? SEIS_PREFETCH : 0;  // rows requested ahead
+    constexpr int D = PIPE ? kPrefetch : 0;  // rows requested ahead
     float b[D + 1][9];
     float an[2][MT];  // A fragments of this row and the next (read from LDS one row ahead)
     auto valid = [&](int i) {
@@ -538,7 +534,7 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
   using R = RefT<Op>;
   const View<R, L::ldK, false> A0(lds + L::oK), A1(lds + L::oK + B * L::ldK), A2(lds + L::oK + 2 * B * L::ldK);
   if constexpr (std::is_same<Op, OpF32>::value) {
-    constexpr int D = SEIS_PREFETCH;
+    constexpr int D = kPrefetch;
     float xb[D + 1][9];
     auto valid = [&](int i) { return i < 4 * RT1 && 16 * (i >> 2) + (i & 3) < B1; };
 #pragma unroll
@@ -830,9 +826,6 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
                                                         for (int p = 0; p < 9; ++p) b[p] = V[t][v][p];
                                                       });
-#if SEIS_FACE_BARRIER
-      __builtin_amdgcn_sched_barrier(0);
-#endif
     }
 
     // volume: dq += sum_d K^d (I~ (dt A*_d)^T) over the rows of I~ below B1,
@@ -869,12 +862,8 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
   }
 }
 
-#ifndef SEIS_FACE_BARRIER
-#define SEIS_FACE_BARRIER 1
-#endif
-#ifndef SEIS_CORR_AHEAD
-#define SEIS_CORR_AHEAD 1  // corrector: (face, node tile) steps whose inbox traces are requested ahead
-#endif
+// corrector: (face, node tile) steps whose inbox traces are requested ahead
+constexpr int kCorrAhead = 1;
 
 // Corrector: Q -= sum_f L_f flux(neighbour trace of face f). The output rows
 // are produced in SPLIT passes (the face fluxes are recomputed per
@@ -886,7 +875,7 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
   constexpr int B = L::B, Bf = L::Bf, RT = L::RT, FT = L::FT;
   constexpr int NS = (SPLIT > RT) ? RT : SPLIT;
   constexpr int MH = (RT + NS - 1) / NS;  // row tiles per pass
-  constexpr int CD = SEIS_CORR_AHEAD;       // inbox steps requested ahead
+  constexpr int CD = kCorrAhead;  // inbox steps requested ahead
   using R = RefT<Op>;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   // only the lifts (and the tail their reads may run into) are staged: ldsL
@@ -1373,7 +1362,8 @@ std::string tune_key(const TunedData& t, int64_t ngroups) {
   int lg = 0;
   while ((int64_t(1) << (lg + 1)) <= ngroups) ++lg;
   std::ostringstream k;
-  k << "v2/" << arch << "/cu" << num_cus() << "/N" << t.N << "/p" << t.precision << "/g" << lg;
+  k << "v3/" << SEIS_SOURCE_HASH << "/" << arch << "/cu" << num_cus() << "/N" << t.N << "/p" << t.precision
+    << "/g" << lg;
   return k.str();
 }
 

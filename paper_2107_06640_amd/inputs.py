@@ -187,6 +187,20 @@ def layered_materials(mesh: Mesh, z_seafloor: float, rock=ROCK, water=WATER):
     return rho.astype(np.float64), lam.astype(np.float64), mu.astype(np.float64)
 
 
+# A soft sedimentary layer between the water and the rock: the elastic-elastic
+# faces between it and the rock have different S impedances on both sides.
+SEDIMENT = dict(rho=2000.0, cp=2500.0, cs=1100.0)
+
+
+def three_layer_materials(mesh: Mesh, z_seafloor: float, z_sediment: float, rock=ROCK, sediment=SEDIMENT,
+                          water=WATER):
+    """Per-element (rho, lambda, mu): water above ``z_seafloor``, sediment down to ``z_sediment``, rock below."""
+    zc = centroids(mesh)[:, 2]
+    layer = np.where(zc > z_seafloor, 0, np.where(zc > z_sediment, 1, 2))
+    tab = np.array([lame(**water), lame(**sediment), lame(**rock)])
+    return tuple(np.ascontiguousarray(tab[layer, i]) for i in range(3))
+
+
 def uniform_materials(mesh: Mesh, rho: float, cp: float, cs: float):
     r, l, m = lame(rho, cp, cs)
     E = mesh.n_elements

@@ -50,3 +50,22 @@ def submesh(mesh, mats, ids):
     rho, lam, mu = mats
     pos = np.searchsorted(ring, ids)
     return sub, (rho[ring], lam[ring], mu[ring]), ring, pos
+
+
+def element_errors(got, ref):
+    """Per-element relative L2 error [E], the worse of the stress and the velocity block.
+
+    Each block of an element is measured against its own norm (orthonormal
+    basis: the coefficient norm is the L2 norm on the reference element), so
+    an error confined to one element is not diluted by the others as in the
+    per-field norm. Blocks whose own norm is below 1e-6 of the largest
+    element norm of that block (zero shear stress in the water, for example)
+    are measured against that floor instead.
+    """
+    out = np.zeros(got.shape[0])
+    for sl in (slice(0, 6), slice(6, 9)):
+        err = np.sqrt(((got[:, :, sl] - ref[:, :, sl]) ** 2).sum(axis=(1, 2)))
+        nrm = np.sqrt((ref[:, :, sl] ** 2).sum(axis=(1, 2)))
+        den = np.maximum(nrm, 1e-6 * nrm.max())
+        out = np.maximum(out, err / den)
+    return out
