@@ -208,6 +208,24 @@ int seis_profile(seis_t *h, int enable);
  * be NULL. Synchronises the stream. */
 int seis_profile_read(seis_t *h, double *ms, int64_t *launches, int64_t *elements);
 
+/* Energy and field norms of the current state (Sec. 3: the velocity-stress
+ * system with the gravitational sea surface, whose energy
+ *   E = sum_K int_K (rho |v|^2 / 2 + W(s)) + int_surface rho g eta^2 / 2
+ * the continuous model conserves and the upwind scheme does not increase;
+ * W = (s:s - lambda/(3 lambda + 2 mu) (tr s)^2) / (4 mu) in an elastic element,
+ * p^2 / (2 lambda) with p = -tr s / 3 in an acoustic one).
+ * out: DEVICE pointer to 12 doubles, written asynchronously on the handle's
+ * stream (synchronise before reading it):
+ *   out[0] = E, out[1] = the volume part, out[2] = the surface part,
+ *   out[3 + p] = int |q_p|^2 over the mesh, p = 0..8 (quantity order above).
+ * Computed in FP64 from the stored state (FP64, or FP32 widened). The sums
+ * go through a partial-sum buffer (12 doubles per work-group, at most 1024
+ * work-groups) that this call allocates on the device at its first use on
+ * the handle and keeps until seis_destroy. Errors: SEIS_EINVAL (NULL
+ * argument), SEIS_EORDER (between a prediction and its correction),
+ * SEIS_EDEVICE. */
+int seis_energy(seis_t *h, double *out);
+
 /* Synchronise the handle's stream. */
 int seis_sync(seis_t *h);
 

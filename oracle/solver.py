@@ -329,6 +329,12 @@ class Oracle:
                               * self.g * eta ** 2))
         return E
 
+    def field_sq_norms(self, Q=None):
+        """int over the mesh of q_p^2 for each quantity p (volume quadrature) -> [9]."""
+        Q = self.Q if Q is None else Q
+        qv = ein("qb,ebp->eqp", self.phi_v, Q)
+        return ein("e,q,eqp->p", self.geo.absdet, self.vw, qv ** 2)
+
     def evaluate(self, x_elem, xi):
         """Solution at reference points xi[n, 3] of elements x_elem[n] -> [n, 9]."""
         phi = bas.eval_basis(self.N, xi)

@@ -12,6 +12,7 @@
 #include "../../include/seis.h"
 #include "assemble.hpp"
 #include "device.hpp"
+#include "energy.hpp"
 #include "layout.hpp"
 #include "model.hpp"
 #include "tuned.hpp"
@@ -72,6 +73,10 @@ struct seis_t {
   std::vector<Rec> recs;
   double tot_ms[3] = {0, 0, 0};
   int64_t tot_launch[3] = {0, 0, 0}, tot_elem[3] = {0, 0, 0};
+  // energy and field norms: FP64 weights, and the partial sums of seis_energy
+  // (allocated at its first call)
+  EnergyData en{};
+  double* en_partial = nullptr;
   // hipGraph of one macro step (options.graph)
   bool use_graph = false;
   hipStream_t cap = nullptr;            // private capture stream
@@ -180,6 +185,14 @@ int build_common(seis_t* h, DevData<double>& c) {
   }
   h->gstart[M.C] = (int64_t)gl.size();
   HIPCHK(h, upload(b, &h->glist, gl), "upload glist");
+  {
+    double *ad, *lmr, *gc, *tw;
+    HIPCHK(h, upload(b, &ad, M.a_absdet), "upload absdet");
+    HIPCHK(h, upload(b, &lmr, M.a_lmr), "upload materials");
+    HIPCHK(h, upload(b, &gc, M.g_coef), "upload surface weights");
+    HIPCHK(h, upload(b, &tw, M.ref.tw), "upload face weights");
+    h->en = EnergyData{M.E, Fg, M.B, M.nq, ad, lmr, gc, tw, eta};
+  }
   c.tgt = tgt; c.mode = mode; c.hperm = hperm; c.half2 = half2; c.rhalf2 = rhalf2; c.gslot = gslot;
   c.perm = perm; c.Eg = Eg; c.Lg = Lg; c.g_elem = gelem; c.g_face = gface; c.g_par = gpar; c.eta = eta;
   c.g = M.g;
@@ -736,6 +749,20 @@ int seis_profile_read(seis_t* h, double* ms, int64_t* launches, int64_t* element
   return SEIS_OK;
 }
 
+int seis_energy(seis_t* h, double* out) {
+  if (!h || !out) return SEIS_EINVAL;
+  if (mid_step(h)) return fail(h, SEIS_EORDER, "state is between a prediction and its correction");
+  if (!h->en_partial) {
+    void* p = nullptr;
+    HIPCHK(h, hipMalloc(&p, sizeof(double) * energy_groups(h->M.E) * kEnergyValues), "alloc energy partials");
+    h->en_partial = static_cast<double*>(p);
+  }
+  const double* q64 = h->precision == SEIS_FP64 ? h->d64.Q : nullptr;
+  const float* q32 = h->precision == SEIS_FP64 ? nullptr : h->d32.Q;
+  HIPCHK(h, launch_energy(h->en, q64, q32, h->en_partial, out, h->stream), "energy launch");
+  return SEIS_OK;
+}
+
 int seis_sync(seis_t* h) {
   if (!h) return SEIS_EINVAL;
   HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
@@ -748,6 +775,7 @@ void seis_destroy(seis_t* h) {
   drop_graph(h);
   if (h->cap) (void)hipStreamDestroy(h->cap);
   for (hipEvent_t ev : h->pool) (void)hipEventDestroy(ev);
+  if (h->en_partial) (void)hipFree(h->en_partial);
   h->buf.release();
   delete h;
 }

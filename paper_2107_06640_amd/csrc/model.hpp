@@ -51,6 +51,7 @@ struct Model {
   std::vector<int64_t> g_elem;         // [F_g] library element id
   std::vector<int8_t> g_face;          // [F_g]
   std::vector<double> g_par;           // [F_g][8]: scale 2A/|J|, n_x, n_y, n_z, Z, a = rho g / Z, lambda, dt
+  std::vector<double> g_coef;          // [F_g] rho g A of the face (surface energy weight)
   std::vector<int32_t> gslot;          // [E] gravity face index of an element, -1 none
   std::vector<int64_t> g_order;        // [F_g]: ABI position of library gravity face f
   // stored time derivatives: gravity elements use their gravity face index,

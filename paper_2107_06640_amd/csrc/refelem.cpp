@@ -272,6 +272,7 @@ RefElement build_reference(int N) {
   for (int m = 0; m < Bf; ++m)
     for (int j = 0; j < Bf; ++j) VT[j * Bf + m] = V[m * Bf + j];
   lu_solve(Bf, VT, rhs, nq);  // rhs[m][q] = ell_m(point q)
+  R.tw = tw;
 
   R.E.assign(4 * Bf * B, 0.0);
   R.L.assign(4 * B * Bf, 0.0);

@@ -31,6 +31,7 @@ struct RefElement {
   std::vector<double> Eg;  // [4][nq][B]
   std::vector<double> Lg;  // [4][B][nq]
   std::vector<double> eta_st;  // [nq][2] face parameters of the eta points
+  std::vector<double> tw;      // [nq] weights of the face rule at the eta points (sum 1/2)
   std::vector<int> perm;   // [6][Bf]: neighbour node index for node m under vertex map h
   std::vector<int> pinv;   // [6][Bf]: inverse of perm[h]
   std::array<std::array<int, 3>, 6> sigma{};  // the 6 vertex maps: my face vertex a -> neighbour's sigma[a]

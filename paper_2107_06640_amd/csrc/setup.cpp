@@ -363,6 +363,7 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
         const double par[8] = {2.0 * area[id] / absdet[e], normal[id * 3], normal[id * 3 + 1], normal[id * 3 + 2],
                                zp, rho[e] * g / zp, lam[e], M.dt_c[cl[e]]};
         for (int p = 0; p < 8; ++p) M.g_par.push_back(par[p]);
+        M.g_coef.push_back(rho[e] * g * area[id]);
       }
   M.g_order.resize(M.g_elem.size());
   std::iota(M.g_order.begin(), M.g_order.end(), 0);

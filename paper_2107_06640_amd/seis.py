@@ -22,7 +22,7 @@ ERRORS = {-1: "SEIS_EINVAL", -2: "SEIS_ENOMEM", -3: "SEIS_EDEVICE", -4: "SEIS_EO
 
 EXPORTED = ["seis_default_options", "seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step",
             "seis_run", "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
-            "seis_destroy", "seis_last_error", "seis_profile", "seis_profile_read"]
+            "seis_destroy", "seis_last_error", "seis_profile", "seis_profile_read", "seis_energy"]
 
 
 class SeisError(RuntimeError):
@@ -65,6 +65,15 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run python -m paper_2107_06640_amd.build")
+    # torch ships its own HIP runtime under the same soname as the one the
+    # library links. Loading torch first makes the library bind to that one
+    # runtime, so that torch's streams and device memory are valid in it;
+    # loaded the other way round, the process would hold two runtimes and
+    # torch's device initialisation fails.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     P = C.c_void_p
     dp = C.POINTER(C.c_double)
@@ -84,13 +93,14 @@ def load_library(path: str = LIB_PATH):
     lib.seis_sync.argtypes = [P]
     lib.seis_profile.argtypes = [P, C.c_int]
     lib.seis_profile_read.argtypes = [P, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.seis_energy.argtypes = [P, C.c_void_p]
     lib.seis_destroy.argtypes = [P]
     lib.seis_destroy.restype = None
     lib.seis_last_error.argtypes = [P]
     lib.seis_last_error.restype = C.c_char_p
     for name in ("seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step", "seis_run",
                  "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
-                 "seis_profile", "seis_profile_read"):
+                 "seis_profile", "seis_profile_read", "seis_energy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -208,6 +218,10 @@ class Solver:
         self._check(self._lib.seis_profile_read(self._h, _ptr(ms, C.c_double), _ptr(la, C.c_int64),
                                                 _ptr(el, C.c_int64)))
         return {k: (float(ms[i]), int(la[i]), int(el[i])) for i, k in enumerate(("predict", "gravity", "correct"))}
+
+    def energy_into(self, out_ptr):
+        """Energy and field norms into 12 doubles at device address ``out_ptr`` (asynchronous)."""
+        self._check(self._lib.seis_energy(self._h, C.c_void_p(int(out_ptr))))
 
     def info(self):
         inf = Info_t()

@@ -303,3 +303,52 @@ def test_lts_matches_global_stepping():
     assert rl < 1.5 * rg, (rl, rg)
     d = np.linalg.norm(lts.Q - gts.Q) / np.linalg.norm(gts.Q)
     assert d < 2 * rg, (d, rg)
+
+
+def test_energy_of_uniform_states_matches_closed_forms():
+    """Energy of uniform states: kinetic rho|v|^2/2 and the strain energy in its stiffness form.
+
+    A uniform strain eps gives s = lambda tr(eps) I + 2 mu eps and the strain
+    energy lambda tr(eps)^2 / 2 + mu eps:eps per unit volume (for mu = 0 this
+    is p^2 / (2 lambda) with p = -lambda tr eps); the oracle evaluates the
+    compliance form of the same energy from s, so a wrong coefficient in
+    either branch fails. The surface term of a uniform eta is rho g eta^2 / 2
+    times the surface area.
+    """
+    mesh, mats = _ocean(2, 2, 3, water_only=False)
+    o = _oracle(mesh, mats, 3)
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((3, 3)) * 1e-6
+    eps = a + a.T
+    v = rng.standard_normal(3)
+    rho, lam, mu = mats
+    wet = mu == 0
+    vol = o.geo.absdet / 6.0
+    expect = 0.0
+    states = np.zeros((mesh.n_elements, 9))
+    for k in range(mesh.n_elements):
+        e = eps if not wet[k] else np.trace(eps) / 3.0 * np.eye(3)   # isotropic strain in the water
+        s = lam[k] * np.trace(e) * np.eye(3) + 2 * mu[k] * e
+        states[k] = [s[0, 0], s[1, 1], s[2, 2], s[0, 1], s[1, 2], s[0, 2], *v]
+        W = lam[k] * np.trace(e) ** 2 / 2 + mu[k] * np.sum(e * e)
+        expect += vol[k] * (W + 0.5 * rho[k] * v @ v)
+    # a uniform state per element: only the constant basis function (value sqrt(6))
+    o.Q[:] = 0.0
+    o.Q[:, 0, :] = states / np.sqrt(6.0)
+    o.eta[:] = 0.0
+    assert abs(o.energy() - expect) <= 1e-12 * expect
+    # surface term: uniform eta on the whole top (area nx * cell * cell)
+    o.Q[:] = 0.0
+    o.eta[:] = 0.7
+    area = 2 * 250.0 * 250.0
+    expect_s = 0.5 * 1000.0 * 9.81 * 0.7 ** 2 * area
+    assert abs(o.energy() - expect_s) <= 1e-12 * expect_s
+
+
+def test_field_norms_equal_coefficient_norms():
+    """Parseval on the orthonormal basis: int_K q_p^2 = |det J| sum_l Q_lp^2."""
+    mesh, mats = _ocean(2, 2, 4, water_only=False)
+    o = _oracle(mesh, mats, 4)
+    o.Q[:] = inputs.random_dofs(mesh.n_elements, o.B, seed=3)
+    direct = np.einsum("e,ebp->p", o.geo.absdet, o.Q ** 2)
+    np.testing.assert_allclose(o.field_sq_norms(), direct, rtol=1e-12)
