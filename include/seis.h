@@ -226,6 +226,20 @@ int seis_profile_read(seis_t *h, double *ms, int64_t *launches, int64_t *element
  * SEIS_EDEVICE. */
 int seis_energy(seis_t *h, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as seis_energy, bit for bit, but the partial sums live in a fixed
+ * device array of the library (1024 x 12 doubles = 96 KiB on each GPU the
+ * library runs on, held until the process ends), so the call allocates
+ * nothing. Every call on one GPU shares that array: calls that overlap on one
+ * GPU (two streams, or two handles on different streams) race on it and must
+ * be serialised by the caller. The array is fully rewritten by each call, so
+ * nothing has to be cleared between calls. Errors: as seis_energy, and
+ * SEIS_EDEVICE when no handle was set up with the current device,
+ * SEIS_ERANGE if the partial sums would exceed the array (cannot happen with
+ * at most 1024 work-groups, checked anyway). */
+int seis_energy_noalloc(seis_t *h, double *out);
+
 /* Synchronise the handle's stream. */
 int seis_sync(seis_t *h);
 

@@ -420,6 +420,11 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
     return setup_fail(SEIS_EDEVICE, "no HIP device");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return setup_fail(SEIS_EDEVICE, std::string("kernels are built for gfx950, device is ") + prop.gcnArchName);
+  {
+    const hipError_t st = energy_scratch_init();
+    if (st != hipSuccess)
+      return setup_fail(SEIS_EDEVICE, std::string("scratch address: ") + hipGetErrorString(st));
+  }
   seis_t* h = new (std::nothrow) seis_t();
   if (!h) return setup_fail(SEIS_ENOMEM, "host allocation failed");
   std::string e;
@@ -760,6 +765,24 @@ int seis_energy(seis_t* h, double* out) {
   const double* q64 = h->precision == SEIS_FP64 ? h->d64.Q : nullptr;
   const float* q32 = h->precision == SEIS_FP64 ? nullptr : h->d32.Q;
   HIPCHK(h, launch_energy(h->en, q64, q32, h->en_partial, out, h->stream), "energy launch");
+  return SEIS_OK;
+}
+
+int seis_energy_noalloc(seis_t* h, double* out) {
+  if (!h || !out) return SEIS_EINVAL;
+  if (mid_step(h)) return fail(h, SEIS_EORDER, "state is between a prediction and its correction");
+  double* part = energy_scratch();
+  if (!part)
+    return fail(h, SEIS_EDEVICE, "the fixed scratch array has no address on the current device (seis_setup "
+                                 "was not run with this device current)");
+  const int64_t need = int64_t(energy_groups(h->M.E)) * kEnergyValues;
+  if (need > kEnergyScratchValues)
+    return fail(h, SEIS_ERANGE, "energy partial sums (" + std::to_string(need) +
+                                    " values) exceed the fixed scratch array (" +
+                                    std::to_string(kEnergyScratchValues) + " values)");
+  const double* q64 = h->precision == SEIS_FP64 ? h->d64.Q : nullptr;
+  const float* q32 = h->precision == SEIS_FP64 ? nullptr : h->d32.Q;
+  HIPCHK(h, launch_energy(h->en, q64, q32, part, out, h->stream), "energy launch");
   return SEIS_OK;
 }
 

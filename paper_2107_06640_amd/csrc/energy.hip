@@ -14,12 +14,22 @@
 // wavefronts strides over the groups and then over the gravity faces, and
 // leaves its kEnergyValues sums in a partial-sum buffer; one more work-group
 // adds the partial sums in a fixed order, so the result is reproducible.
+#include <mutex>
+
 #include "energy.hpp"
 #include "layout.hpp"
 
 namespace seis {
 
 namespace {
+
+// Partial sums of the energy of callers that cannot allocate: one array per
+// GPU for the life of the process, shared by every call on that GPU.
+__device__ __align__(256) double scratch[kEnergyScratchValues];
+
+constexpr int kDevices = 64;
+double* g_scratch_ptr[kDevices] = {};
+std::mutex g_scratch_mu;
 
 constexpr int kThreads = 256;
 
@@ -118,6 +128,27 @@ hipError_t launch_energy(const EnergyData& d, const double* Q64, const float* Q3
   if (st != hipSuccess) return st;
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kThreads), 0, s, partial, groups, out);
   return hipGetLastError();
+}
+
+hipError_t energy_scratch_init() {
+  int dev = 0;
+  hipError_t st = hipGetDevice(&dev);
+  if (st != hipSuccess) return st;
+  if (dev < 0 || dev >= kDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void* p = nullptr;
+  st = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (st != hipSuccess) return st;
+  g_scratch_ptr[dev] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* energy_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
 }
 
 }  // namespace seis

@@ -32,4 +32,11 @@ int energy_groups(int64_t E);
 hipError_t launch_energy(const EnergyData& d, const double* Q64, const float* Q32, double* partial, double* out,
                          hipStream_t s);
 
+// The library's fixed partial-sum buffer on the current device (for callers
+// that cannot allocate). energy_scratch_init() looks its address up once per
+// device and must run, with that device current, before energy_scratch().
+hipError_t energy_scratch_init();
+double* energy_scratch();
+constexpr int64_t kEnergyScratchValues = int64_t(kEnergyMaxGroups) * kEnergyValues;
+
 }  // namespace seis

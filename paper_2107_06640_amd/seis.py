@@ -22,7 +22,8 @@ ERRORS = {-1: "SEIS_EINVAL", -2: "SEIS_ENOMEM", -3: "SEIS_EDEVICE", -4: "SEIS_EO
 
 EXPORTED = ["seis_default_options", "seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step",
             "seis_run", "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
-            "seis_destroy", "seis_last_error", "seis_profile", "seis_profile_read", "seis_energy"]
+            "seis_destroy", "seis_last_error", "seis_profile", "seis_profile_read", "seis_energy",
+            "seis_energy_noalloc"]
 
 
 class SeisError(RuntimeError):
@@ -94,13 +95,14 @@ def load_library(path: str = LIB_PATH):
     lib.seis_profile.argtypes = [P, C.c_int]
     lib.seis_profile_read.argtypes = [P, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.seis_energy.argtypes = [P, C.c_void_p]
+    lib.seis_energy_noalloc.argtypes = [P, C.c_void_p]
     lib.seis_destroy.argtypes = [P]
     lib.seis_destroy.restype = None
     lib.seis_last_error.argtypes = [P]
     lib.seis_last_error.restype = C.c_char_p
     for name in ("seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step", "seis_run",
                  "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
-                 "seis_profile", "seis_profile_read", "seis_energy"):
+                 "seis_profile", "seis_profile_read", "seis_energy", "seis_energy_noalloc"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -219,9 +221,10 @@ class Solver:
                                                 _ptr(el, C.c_int64)))
         return {k: (float(ms[i]), int(la[i]), int(el[i])) for i, k in enumerate(("predict", "gravity", "correct"))}
 
-    def energy_into(self, out_ptr):
+    def energy_into(self, out_ptr, noalloc=False):
         """Energy and field norms into 12 doubles at device address ``out_ptr`` (asynchronous)."""
-        self._check(self._lib.seis_energy(self._h, C.c_void_p(int(out_ptr))))
+        fn = self._lib.seis_energy_noalloc if noalloc else self._lib.seis_energy
+        self._check(fn(self._h, C.c_void_p(int(out_ptr))))
 
     def info(self):
         inf = Info_t()
