@@ -76,12 +76,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cfg3_order6.json")
 
 
 def kernel_source_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for f in ("tuned.hip", "layout.hpp", "elastic.hpp"):
-        with open(os.path.join(ROOT, "paper_2107_06640_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the library sources (the one the autotuner keys its cache on)."""
+    from paper_2107_06640_amd.build import source_hash
+    return source_hash()
 
 
 def measured_traffic(kernel_kind, precision, kernel, order):
@@ -102,9 +99,19 @@ def measured_traffic(kernel_kind, precision, kernel, order):
     return None if v is None else float(v)
 
 
-def workload(scale, seed=0):
+WORKLOADS = {
+    # the benchmark box: +-20% jitter leaves one outlier element as the
+    # finest cluster, so nearly every element steps with the coarsest step
+    "cfg3": 0.2,
+    # the same box with +-10% jitter: three clusters that each carry a real
+    # share of the updates (LTS saves a third of them)
+    "cfg3-lts": 0.1,
+}
+
+
+def workload(scale, seed=0, name="cfg3"):
     from paper_2107_06640_amd import inputs
-    mesh, mats = inputs.cfg3(scale=scale, seed=seed)
+    mesh, mats = inputs.cfg3(scale=scale, seed=seed, jitter=WORKLOADS[name])
     return mesh, mats
 
 
@@ -177,6 +184,29 @@ def precision_sweep(args):
         del ref
 
 
+def host_description():
+    """nproc, CPU model and memory of the host (for the CPU baseline record)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem_gb = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model, "mem_GiB": mem_gb}
+
+
 def cpu_baseline(order, budget_s=15.0):
     """Oracle element-updates/s on a 6 x 6 x 8-cube sample of the workload (GTS)."""
     from oracle.solver import Oracle
@@ -200,6 +230,7 @@ def cpu_baseline(order, budget_s=15.0):
     except Exception:
         cores = os.cpu_count() or 1
     return dict(value=(o.updates - u0) / dt, unit="element-updates/s", cores=int(cores), kind="oracle",
+                host=host_description(),
                 sample=f"{mesh.n_elements} tets (6x6x8 cubes of the graded coupled box, order {order}, "
                        f"global time stepping), {n} steps in {dt:.1f} s")
 
@@ -213,6 +244,9 @@ def main():
     ap.add_argument("--kernel", default="tuned", choices=["tuned", "plain"])
     ap.add_argument("--order", type=int, default=6)
     ap.add_argument("--scale", type=int, default=1)
+    ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
+    ap.add_argument("--per-cluster", action="store_true",
+                    help="one launch per cluster instead of one per phase per sub-step")
     ap.add_argument("--max-clusters", type=int, default=4)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--mc-min", type=int, default=None,
@@ -254,13 +288,13 @@ def main():
     from paper_2107_06640_amd import seis
 
     t_setup = time.perf_counter()
-    mesh, mats = workload(args.scale)
+    mesh, mats = workload(args.scale, name=args.workload)
     rho, lam, mu = mats
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     s = seis.from_mesh(mesh, mats, args.order, precision=args.precision, kernel=args.kernel,
                        max_clusters=args.max_clusters, stream=stream.cuda_stream, tile=args.tile,
-                       graph=args.graph, mc_min=args.mc_min)
+                       graph=args.graph, mc_min=args.mc_min, fused=not args.per_cluster)
     inf = s.info()
     q = tiled_dofs(mesh.n_elements, inf["n_basis"], 0, mu == 0)
     s.write(q)
@@ -315,7 +349,10 @@ def main():
     else:
         roof = dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom, args.precision, args.kernel, args.order)
+    roof["traffic"] = measured_traffic(dom, args.precision, args.kernel, args.order) \
+        if args.workload == "cfg3" else None
+    roof["traffic_source"] = ("stored rocprofv3 FETCH_SIZE/WRITE_SIZE of these kernel sources "
+                              "(profiles/traffic_cfg3_order6.json)") if roof["traffic"] is not None else None
     roof["kernel"] = dom
     roof["avg_launch_ms"] = kms / kl
 
@@ -332,11 +369,14 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"graded jittered ocean-over-solid box, {inf['n_elements']} tets, "
+        "config": {"workload": f"{args.workload}: graded jittered ocean-over-solid box "
+                               f"(jitter {WORKLOADS[args.workload]}), {inf['n_elements']} tets, "
                                f"order {args.order} (B={inf['n_basis']}), rate-2 LTS {inf['n_clusters']} clusters "
                                f"{inf['cluster_size']}, {inf['n_gravity_faces']} gravity faces",
                    "kernel": args.kernel, "precision": args.precision, "elements": inf["n_elements"],
-                   "graph": bool(args.graph), "eager_ms_per_step": eager_ms / args.steps,
+                   "graph": bool(args.graph), "fused": bool(inf["fused"]),
+                   "eager_ms_per_step": eager_ms / args.steps,
+                   "launches_per_step": {k: v[1] / args.steps for k, v in prof.items()},
                    "launch": {"predict": inf["launch"][:3], "correct": inf["launch"][3:7],
                               "mc_min": inf["launch"][7],
                               "source": ["default", "measured", "cache"][inf["launch_source"]]},

@@ -108,6 +108,12 @@ typedef struct {
                        wavefront works through its 16 elements in sequence, so a tiny cluster is
                        bound by that latency there). Default 2048; 0 puts every cluster on the
                        matrix cores. Must be >= 0. */
+  int fused;        /* nonzero (default): seis_step launches each phase of a sub-step once over every
+                       cluster due in it (the due clusters 0..k are one element range, Sec. 4.4), the
+                       predictor over the range on the matrix cores when it has at least mc_min
+                       elements, else on the plain FP32 kernels; 0: one launch per cluster, each
+                       cluster's kernel chosen by its own size. seis_predict/seis_correct always work
+                       per cluster. */
 } seis_options_t;
 
 typedef struct {
@@ -131,10 +137,11 @@ typedef struct {
                            [6] the corrector's passes over its output rows; [7] options.mc_min */
   int launch_source;    /* 0 default or fixed (options.tile, SEIS_TUNE), 1 measured at set-up,
                            2 read from the tuning cache */
+  int fused;            /* options.fused */
 } seis_info_t;
 
 /* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream,
- * eager launches (no graph), mc_min 2048. */
+ * eager launches (no graph), mc_min 2048, fused sub-step launches. */
 void seis_default_options(seis_options_t *opt);
 
 /* Build the solver for a mesh (Sec. 4.1-4.4): validate, match faces,

@@ -77,6 +77,9 @@ struct seis_t {
   // (allocated at its first call)
   EnergyData en{};
   double* en_partial = nullptr;
+  // seis_step launches one kernel per phase per sub-step over every due
+  // cluster (options.fused), else one per cluster
+  bool fused = true;
   // hipGraph of one macro step (options.graph)
   bool use_graph = false;
   hipStream_t cap = nullptr;            // private capture stream
@@ -301,20 +304,30 @@ hipError_t timed(seis_t* h, int kind, int64_t n, F fn) {
   return hipSuccess;
 }
 
-int do_predict(seis_t* h, int c) {
+Sched make_sched(const seis_t* h) {
+  Sched sc;
+  sc.sub = h->sub;
+  sc.C = h->M.C;
+  for (int c = 0; c <= h->M.C; ++c) sc.cstart[c] = h->M.cluster_start[c];
+  return sc;
+}
+
+// Predictors of clusters c0..c1 (consecutive, so one element range) at the
+// current sub-step, then their gravity faces.
+int do_predict(seis_t* h, int c0, int c1) {
   Model& M = h->M;
-  const int64_t e0 = M.cluster_start[c], ne = M.cluster_start[c + 1] - e0;
-  const int parity = (h->sub >> c) & 1;
+  const int64_t e0 = M.cluster_start[c0], ne = M.cluster_start[c1 + 1] - e0;
+  const Sched sc = make_sched(h);
   hipError_t st = hipSuccess;
-  const int32_t* gl = h->glist + h->gstart[c];
-  const int64_t ng = h->gstart[c + 1] - h->gstart[c];
+  const int32_t* gl = h->glist + h->gstart[c0];
+  const int64_t ng = h->gstart[c1 + 1] - h->gstart[c0];
   const int N = M.N;
   st = timed(h, 0, ne, [&]() -> hipError_t {
     if (h->kernel == SEIS_KERNEL_PLAIN) {
-      if (h->precision == SEIS_FP64) return launch_predict_plain<double>(N, h->d64, e0, ne, parity, h->stream);
-      return launch_predict_plain<float>(N, h->d32, e0, ne, parity, h->stream);
+      if (h->precision == SEIS_FP64) return launch_predict_plain<double>(N, h->d64, e0, ne, sc, h->stream);
+      return launch_predict_plain<float>(N, h->d32, e0, ne, sc, h->stream);
     }
-    return tuned_predict(h->tuned, h->precision, N, c, e0, e0 + ne, parity, h->stream);
+    return tuned_predict(h->tuned, h->precision, N, c0, c1, e0, e0 + ne, sc, h->stream);
   });
   if (st == hipSuccess)
     st = timed(h, 1, ng, [&]() -> hipError_t {
@@ -325,17 +338,17 @@ int do_predict(seis_t* h, int c) {
   return SEIS_OK;
 }
 
-int do_correct(seis_t* h, int c) {
+int do_correct(seis_t* h, int c0, int c1) {
   Model& M = h->M;
-  const int64_t e0 = M.cluster_start[c], ne = M.cluster_start[c + 1] - e0;
-  const int parity = (h->sub >> c) & 1;
+  const int64_t e0 = M.cluster_start[c0], ne = M.cluster_start[c1 + 1] - e0;
+  const Sched sc = make_sched(h);
   const int N = M.N;
   hipError_t st = timed(h, 2, ne, [&]() -> hipError_t {
     if (h->kernel == SEIS_KERNEL_PLAIN) {
-      if (h->precision == SEIS_FP64) return launch_correct_plain<double>(N, h->d64, e0, ne, parity, h->stream);
-      return launch_correct_plain<float>(N, h->d32, e0, ne, parity, h->stream);
+      if (h->precision == SEIS_FP64) return launch_correct_plain<double>(N, h->d64, e0, ne, sc, h->stream);
+      return launch_correct_plain<float>(N, h->d32, e0, ne, sc, h->stream);
     }
-    return tuned_correct(h->tuned, h->precision, N, c, e0, e0 + ne, parity, h->stream);
+    return tuned_correct(h->tuned, h->precision, N, c0, c1, e0, e0 + ne, sc, h->stream);
   });
   if (st != hipSuccess) return hip_fail(h, st, "correct launch");
   return SEIS_OK;
@@ -393,6 +406,7 @@ void seis_default_options(seis_options_t* o) {
   o->tile = 0;
   o->graph = 0;
   o->mc_min = 2048;
+  o->fused = 1;
 }
 
 int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, const seis_options_t* opt,
@@ -447,6 +461,7 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
   h->tile = o.tile;
   h->stream = (hipStream_t)o.stream;
   h->use_graph = o.graph != 0;
+  h->fused = o.fused != 0;
   h->tuned.mc_min = o.mc_min;
   int rc = build_common(h, h->d64);
   if (rc == SEIS_OK) {
@@ -515,7 +530,7 @@ int seis_predict(seis_t* h, int c) {
   if (c < 0 || c >= h->M.C) return fail(h, SEIS_ERANGE, "cluster id out of range");
   if (!due_predict(h->sub, c) || h->predicted[c])
     return fail(h, SEIS_EORDER, "cluster is not due for a prediction at this point of the LTS schedule");
-  int rc = do_predict(h, c);
+  int rc = do_predict(h, c, c);
   if (rc != SEIS_OK) return rc;
   h->predicted[c] = 1;
   maybe_advance(h);
@@ -532,7 +547,7 @@ int seis_correct(seis_t* h, int c) {
     if (h->M.cluster_start[cc + 1] > h->M.cluster_start[cc] && due_predict(h->sub, cc) && !h->predicted[cc])
       return fail(h, SEIS_EORDER, "all predictions of the sub-step must run before its corrections");
   if (!h->predicted[c]) return fail(h, SEIS_EORDER, "cluster has not been predicted for this step");
-  int rc = do_correct(h, c);
+  int rc = do_correct(h, c, c);
   if (rc != SEIS_OK) return rc;
   h->corrected[c] = 1;
   maybe_advance(h);
@@ -558,7 +573,35 @@ int seis_run(seis_t* h, int n) {
 
 namespace {
 
+// One macro step with one launch per phase per sub-step: the clusters due in
+// sub-step s are 0..k with k the largest c such that 2^c divides s (for the
+// predictors) or s + 1 (for the correctors), so they form one element range
+// (clusters are contiguous in library order) and one launch covers them all;
+// each element takes its step parity from the schedule. Ordering between the
+// phases stays at kernel boundaries on the stream.
+int step_fused(seis_t* h) {
+  const int C = h->M.C;
+  auto top_due = [&](int s1) {
+    int k = 0;
+    while (k + 1 < C && s1 % (1 << (k + 1)) == 0) ++k;
+    return k;
+  };
+  for (int s = 0; s < (1 << (C - 1)); ++s) {
+    h->sub = s;
+    int rc = do_predict(h, 0, top_due(s));
+    if (rc == SEIS_OK) rc = do_correct(h, 0, top_due(s + 1));
+    if (rc != SEIS_OK) {
+      reset_cursor(h);
+      return rc;
+    }
+  }
+  reset_cursor(h);
+  h->macro_done++;
+  return SEIS_OK;
+}
+
 int step_eager(seis_t* h) {
+  if (h->fused) return step_fused(h);
   const int C = h->M.C;
   for (int s = 0; s < (1 << (C - 1)); ++s) {
     for (int c = 0; c < C; ++c)
@@ -720,6 +763,7 @@ int seis_info(const seis_t* h, seis_info_t* info) {
   info->launch[6] = h->tuned.cc.split;
   info->launch[7] = h->tuned.mc_min;
   info->launch_source = h->tuned.source;
+  info->fused = h->fused ? 1 : 0;
   return SEIS_OK;
 }
 

@@ -17,6 +17,25 @@
 
 namespace seis {
 
+// Position in the rate-2 LTS schedule (Sec. 4.4): the sub-step of the macro
+// step and the element ranges of the clusters (library order, cluster c is
+// [cstart[c], cstart[c+1])). An element of cluster c is on the second step of
+// a pair of its steps when (sub >> c) & 1; the hand-over to a coarser
+// neighbour and the reading of second-half traces depend on it. A launch may
+// span several clusters, so the kernels take it per element.
+struct Sched {
+  static constexpr int kMax = 16;
+  int sub = 0;
+  int C = 1;
+  int64_t cstart[kMax + 1] = {};
+  __host__ __device__ __forceinline__ int parity(int64_t e) const {
+    int c = 0;
+#pragma unroll
+    for (int k = 1; k < kMax; ++k) c = (k < C && e >= cstart[k]) ? k : c;
+    return (sub >> c) & 1;
+  }
+};
+
 template <typename T>
 struct DevData {
   int64_t E;
@@ -51,9 +70,9 @@ struct DevData {
 
 // Plain kernels: one work-group per element, FP64 or FP32.
 template <typename T>
-hipError_t launch_predict_plain(int N, const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipStream_t s);
+hipError_t launch_predict_plain(int N, const DevData<T>& d, int64_t e0, int64_t ne, const Sched& sc, hipStream_t s);
 template <typename T>
-hipError_t launch_correct_plain(int N, const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipStream_t s);
+hipError_t launch_correct_plain(int N, const DevData<T>& d, int64_t e0, int64_t ne, const Sched& sc, hipStream_t s);
 // Gravity faces listed in glist[0..ng) (FP64 ODE and lift).
 template <typename T>
 hipError_t launch_gravity(int N, const DevData<T>& d, const int32_t* glist, int64_t ng, hipStream_t s);

@@ -21,14 +21,19 @@ namespace {
 
 // Threads per element: 256 for throughput; a launch over a few elements (a
 // tiny LTS cluster) is bound by the latency of one work-group, so it uses 1024.
+// The thread count is a launch parameter of one compiled kernel, not a
+// template argument, so that an element's arithmetic (and its rounding) is
+// the same whichever launch covers it.
 constexpr int NT_WIDE = 256, NT_TALL = 1024, TALL_BELOW = 256;
 
-template <typename T, int N, int NT>
-__global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, int parity) {
+template <typename T, int N>
+__global__ __launch_bounds__(NT_TALL) void k_predict_plain(DevData<T> d, int64_t e0, Sched sc) {
+  const int NT = blockDim.x;
   constexpr int B = nbasis(N), Bf = nface(N);
   constexpr int B1 = nbasis(N - 1);
   constexpr int RT = row_tiles(B), FT = row_tiles(Bf);
   const int64_t e = e0 + blockIdx.x;
+  const int parity = sc.parity(e);
   const int tid = threadIdx.x;
   __shared__ T sD[B * 9], sI[B * 9], sIh[B * 9];
   __shared__ T sY[3 * B * 9];  // reused for the volume term
@@ -148,11 +153,13 @@ __global__ __launch_bounds__(NT) void k_predict_plain(DevData<T> d, int64_t e0, 
   }
 }
 
-template <typename T, int N, int NT>
-__global__ __launch_bounds__(NT) void k_correct_plain(DevData<T> d, int64_t e0, int parity) {
+template <typename T, int N>
+__global__ __launch_bounds__(NT_TALL) void k_correct_plain(DevData<T> d, int64_t e0, Sched sc) {
+  const int NT = blockDim.x;
   constexpr int B = nbasis(N), Bf = nface(N);
   constexpr int RT = row_tiles(B), FT = row_tiles(Bf);
   const int64_t e = e0 + blockIdx.x;
+  const int parity = sc.parity(e);
   const int tid = threadIdx.x;
   __shared__ T sW[4 * Bf * 9];
   for (int i = tid; i < 4 * Bf * 9; i += NT) {
@@ -256,21 +263,21 @@ __global__ __launch_bounds__(256) void k_gravity(DevData<T> d, const int32_t* gl
 }
 
 template <typename T, int N>
-hipError_t pred_n(const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipStream_t s) {
+hipError_t pred_n(const DevData<T>& d, int64_t e0, int64_t ne, const Sched& sc, hipStream_t s) {
   if (ne <= 0) return hipSuccess;
   if (ne < TALL_BELOW)
-    hipLaunchKernelGGL((k_predict_plain<T, N, NT_TALL>), dim3((unsigned)ne), dim3(NT_TALL), 0, s, d, e0, parity);
+    hipLaunchKernelGGL((k_predict_plain<T, N>), dim3((unsigned)ne), dim3(NT_TALL), 0, s, d, e0, sc);
   else
-    hipLaunchKernelGGL((k_predict_plain<T, N, NT_WIDE>), dim3((unsigned)ne), dim3(NT_WIDE), 0, s, d, e0, parity);
+    hipLaunchKernelGGL((k_predict_plain<T, N>), dim3((unsigned)ne), dim3(NT_WIDE), 0, s, d, e0, sc);
   return hipGetLastError();
 }
 template <typename T, int N>
-hipError_t corr_n(const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipStream_t s) {
+hipError_t corr_n(const DevData<T>& d, int64_t e0, int64_t ne, const Sched& sc, hipStream_t s) {
   if (ne <= 0) return hipSuccess;
   if (ne < TALL_BELOW)
-    hipLaunchKernelGGL((k_correct_plain<T, N, NT_TALL>), dim3((unsigned)ne), dim3(NT_TALL), 0, s, d, e0, parity);
+    hipLaunchKernelGGL((k_correct_plain<T, N>), dim3((unsigned)ne), dim3(NT_TALL), 0, s, d, e0, sc);
   else
-    hipLaunchKernelGGL((k_correct_plain<T, N, NT_WIDE>), dim3((unsigned)ne), dim3(NT_WIDE), 0, s, d, e0, parity);
+    hipLaunchKernelGGL((k_correct_plain<T, N>), dim3((unsigned)ne), dim3(NT_WIDE), 0, s, d, e0, sc);
   return hipGetLastError();
 }
 template <typename T, int N>
@@ -293,22 +300,26 @@ hipError_t grav_n(const DevData<T>& d, const int32_t* glist, int64_t ng, hipStre
   }
 
 template <typename T>
-hipError_t launch_predict_plain(int N, const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipStream_t s) {
-  SEIS_DISPATCH(pred_n, d, e0, ne, parity, s)
+hipError_t launch_predict_plain(int N, const DevData<T>& d, int64_t e0, int64_t ne, const Sched& sc, hipStream_t s) {
+  SEIS_DISPATCH(pred_n, d, e0, ne, sc, s)
 }
 template <typename T>
-hipError_t launch_correct_plain(int N, const DevData<T>& d, int64_t e0, int64_t ne, int parity, hipStream_t s) {
-  SEIS_DISPATCH(corr_n, d, e0, ne, parity, s)
+hipError_t launch_correct_plain(int N, const DevData<T>& d, int64_t e0, int64_t ne, const Sched& sc, hipStream_t s) {
+  SEIS_DISPATCH(corr_n, d, e0, ne, sc, s)
 }
 template <typename T>
 hipError_t launch_gravity(int N, const DevData<T>& d, const int32_t* glist, int64_t ng, hipStream_t s) {
   SEIS_DISPATCH(grav_n, d, glist, ng, s)
 }
 
-template hipError_t launch_predict_plain<double>(int, const DevData<double>&, int64_t, int64_t, int, hipStream_t);
-template hipError_t launch_predict_plain<float>(int, const DevData<float>&, int64_t, int64_t, int, hipStream_t);
-template hipError_t launch_correct_plain<double>(int, const DevData<double>&, int64_t, int64_t, int, hipStream_t);
-template hipError_t launch_correct_plain<float>(int, const DevData<float>&, int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_predict_plain<double>(int, const DevData<double>&, int64_t, int64_t, const Sched&,
+                                                 hipStream_t);
+template hipError_t launch_predict_plain<float>(int, const DevData<float>&, int64_t, int64_t, const Sched&,
+                                                hipStream_t);
+template hipError_t launch_correct_plain<double>(int, const DevData<double>&, int64_t, int64_t, const Sched&,
+                                                 hipStream_t);
+template hipError_t launch_correct_plain<float>(int, const DevData<float>&, int64_t, int64_t, const Sched&,
+                                                hipStream_t);
 template hipError_t launch_gravity<double>(int, const DevData<double>&, const int32_t*, int64_t, hipStream_t);
 template hipError_t launch_gravity<float>(int, const DevData<float>&, const int32_t*, int64_t, hipStream_t);
 

@@ -655,7 +655,7 @@ struct PredLds {
 };
 
 template <class Op, int N, int W>
-__global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, int64_t e1, int parity, int remap) {
+__global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, int64_t e1, Sched sc, int remap) {
   using L = Lay<Op, N>;
   constexpr int B = L::B, Bf = L::Bf, B1 = L::B1, RT = L::RT, FT = L::FT, RT1 = L::RT1;
   using R = RefT<Op>;
@@ -776,7 +776,8 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
       // hand-over into the neighbour's inbox (its node numbering, its time
       // step): a neighbour in the same cluster gets the full-step trace; a
       // coarser one half of it, accumulated over this element's two steps
-      // (parity is uniform over the launch); a finer one gets the full-step
+      // (the parity of the step is per element: a launch may span clusters);
+      // a finer one gets the full-step
       // trace here, which the half-step fix-up turns into its two halves.
       // Loads are unconditional (valid indices for every lane); only the
       // stores are masked.
@@ -786,6 +787,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
         const int h = (mh >> (8 * f + 2)) & 7;
         const bool send = live && md0 != 0;
         const bool half = md0 == 3;
+        const int parity = sc.parity(ec);
         const int32_t tg = send ? tg0 : 0;
 #pragma unroll
         for (int t = 0; t < FT; ++t)
@@ -1097,7 +1099,7 @@ hipError_t prep(KernelPtr k, int lds) {
 
 
 template <class Op, int N, int W>
-hipError_t launch_pred(const TArgs& a, int64_t e0, int64_t e1, int parity, const LaunchCfg& c, hipStream_t s) {
+hipError_t launch_pred(const TArgs& a, int64_t e0, int64_t e1, const Sched& sc, const LaunchCfg& c, hipStream_t s) {
   if (e1 <= e0) return hipSuccess;
   using L = Lay<Op, N>;
   const int64_t ng = ((e1 - 1) >> 4) - (e0 >> 4) + 1;
@@ -1106,7 +1108,7 @@ hipError_t launch_pred(const TArgs& a, int64_t e0, int64_t e1, int parity, const
   static_assert(lds <= 160 * 1024, "predictor LDS exceeds the 160 KB of a CU");
   static hipError_t attr = prep(k_predict_tuned<Op, N, W>, lds);
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_predict_tuned<Op, N, W>), dim3(grid), dim3(64 * W), lds, s, a, e0, e1, parity, c.remap);
+  hipLaunchKernelGGL((k_predict_tuned<Op, N, W>), dim3(grid), dim3(64 * W), lds, s, a, e0, e1, sc, c.remap);
   return hipGetLastError();
 }
 
@@ -1124,11 +1126,11 @@ hipError_t launch_corr(const TArgs& a, int64_t e0, int64_t e1, const LaunchCfg& 
 }
 
 template <class Op>
-hipError_t pred_dispatch(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, int parity,
+hipError_t pred_dispatch(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, const Sched& sc,
                          hipStream_t s) {
   const int W = c.waves;
 #define SEIS_P(NN, WW) \
-  if (N == NN && W == WW) return launch_pred<Op, NN, WW>(a, e0, e1, parity, c, s);
+  if (N == NN && W == WW) return launch_pred<Op, NN, WW>(a, e0, e1, sc, c, s);
   SEIS_P(2, 2) SEIS_P(2, 4)
   SEIS_P(3, 2) SEIS_P(3, 4)
   SEIS_P(4, 2) SEIS_P(4, 4)
@@ -1305,25 +1307,35 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
   return hipSuccess;
 }
 
-hipError_t tuned_predict(const TunedData& t, int precision, int N, int c, int64_t e0, int64_t e1, int parity,
-                         hipStream_t s) {
-  if (precision == 0) return launch_predict_plain<double>(N, t.d64, e0, e1 - e0, parity, s);
-  if (e1 - e0 < t.mc_min) return launch_predict_plain<float>(N, t.d32, e0, e1 - e0, parity, s);
-  hipError_t st = precision == 1 ? pred_dispatch<OpF32>(N, t.pc, t.a, e0, e1, parity, s)
-                                 : pred_dispatch<OpBF16>(N, t.pc, t.a, e0, e1, parity, s);
+hipError_t tuned_predict(const TunedData& t, int precision, int N, int c0, int c1, int64_t e0, int64_t e1,
+                         const Sched& sc, hipStream_t s) {
+  if (precision == 0) return launch_predict_plain<double>(N, t.d64, e0, e1 - e0, sc, s);
+  if (e1 - e0 < t.mc_min) return launch_predict_plain<float>(N, t.d32, e0, e1 - e0, sc, s);
+  hipError_t st = precision == 1 ? pred_dispatch<OpF32>(N, t.pc, t.a, e0, e1, sc, s)
+                                 : pred_dispatch<OpBF16>(N, t.pc, t.a, e0, e1, sc, s);
   if (st != hipSuccess) return st;
-  const int64_t f0 = t.fix_start[c], nf = t.fix_start[c + 1] - f0;
+  const int64_t f0 = t.fix_start[c0], nf = t.fix_start[c1 + 1] - f0;
   return fixup_dispatch(N, t.a, t.a.fix_list + f0, nf, s);
 }
 
-hipError_t tuned_correct(const TunedData& t, int precision, int N, int c, int64_t e0, int64_t e1, int parity,
-                         hipStream_t s) {
-  if (precision == 0) return launch_correct_plain<double>(N, t.d64, e0, e1 - e0, parity, s);
-  if (e1 - e0 < t.mc_min) return launch_correct_plain<float>(N, t.d32, e0, e1 - e0, parity, s);
-  if (parity) {
-    const int64_t h0 = t.h2_start[c], nh = t.h2_start[c + 1] - h0;
+hipError_t tuned_correct(const TunedData& t, int precision, int N, int c0, int c1, int64_t e0, int64_t e1,
+                         const Sched& sc, hipStream_t s) {
+  if (precision == 0) return launch_correct_plain<double>(N, t.d64, e0, e1 - e0, sc, s);
+  if (e1 - e0 < t.mc_min) return launch_correct_plain<float>(N, t.d32, e0, e1 - e0, sc, s);
+  // second-half traces into the inbox of the clusters on the second step of
+  // their pair (h2_list is ordered by cluster): one launch per run of such
+  // clusters
+  for (int c = c0; c <= c1;) {
+    if (!((sc.sub >> c) & 1)) {
+      ++c;
+      continue;
+    }
+    int c2 = c;
+    while (c2 + 1 <= c1 && ((sc.sub >> (c2 + 1)) & 1)) ++c2;
+    const int64_t h0 = t.h2_start[c], nh = t.h2_start[c2 + 1] - h0;
     hipError_t st = h2_dispatch(N, t.a, t.a.h2_list + h0, nh, s);
     if (st != hipSuccess) return st;
+    c = c2 + 1;
   }
   return precision == 1 ? corr_dispatch<OpF32>(N, t.cc, t.a, e0, e1, s)
                         : corr_dispatch<OpBF16>(N, t.cc, t.a, e0, e1, s);
@@ -1465,8 +1477,8 @@ hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s) {
         if (cap <= 2) {
           hipError_t st = time_launch(
               [&]() {
-                return t.precision == 1 ? pred_dispatch<OpF32>(t.N, c, t.a, e0, ei, 0, s)
-                                        : pred_dispatch<OpBF16>(t.N, c, t.a, e0, ei, 0, s);
+                return t.precision == 1 ? pred_dispatch<OpF32>(t.N, c, t.a, e0, ei, Sched{}, s)
+                                        : pred_dispatch<OpBF16>(t.N, c, t.a, e0, ei, Sched{}, s);
               },
               s, reps, ms);
           if (st != hipSuccess) return st;

@@ -60,16 +60,18 @@ struct TunedData {
 
 hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevData<double>& d64,
                        const DevData<float>& d32, int tile, std::vector<void*>& owned, int64_t& bytes);
-// Cluster c = elements [e0, e1). FP64 runs the plain kernels, and so does a
-// cluster of fewer than mc_min elements (in FP32). Otherwise the
+// Clusters c0..c1 = elements [e0, e1) (a launch may span several clusters;
+// sc gives each element's step parity). FP64 runs the plain kernels, and so
+// does a range of fewer than mc_min elements (in FP32). Otherwise the
 // matrix-core predictor handles every element; faces handing over to a finer
 // neighbour are then rewritten with the first- and second-half traces, and
-// before the corrector of an odd sub-step the second-half traces are copied
-// into the inbox of the finer elements that read them.
-hipError_t tuned_predict(const TunedData& t, int precision, int N, int c, int64_t e0, int64_t e1, int parity,
-                         hipStream_t s);
-hipError_t tuned_correct(const TunedData& t, int precision, int N, int c, int64_t e0, int64_t e1, int parity,
-                         hipStream_t s);
+// before the corrector the second-half traces of the clusters on the second
+// step of their pair are copied into the inbox of the finer elements that
+// read them.
+hipError_t tuned_predict(const TunedData& t, int precision, int N, int c0, int c1, int64_t e0, int64_t e1,
+                         const Sched& sc, hipStream_t s);
+hipError_t tuned_correct(const TunedData& t, int precision, int N, int c0, int c1, int64_t e0, int64_t e1,
+                         const Sched& sc, hipStream_t s);
 // Choose pc and cc for the largest cluster by
 // timing the candidates on the (zero) state left by set-up, or read them from
 // the tuning cache. The state stays zero: every kernel is linear.

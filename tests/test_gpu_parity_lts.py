@@ -13,8 +13,11 @@ Cases:
   within 1e-10, per-element relative L2 within 1e-9.
 * FP32 and BF16 matrix-core kernels at orders 5, 6 and 7, 10 macro steps
   (80 sub-steps of the finest cluster), with every cluster on the matrix
-  cores (mc_min 0), and with the two outer clusters on the plain FP32
-  kernels (mc_min 150), so that hand-overs cross between the kernel kinds.
+  cores (mc_min 0), and with mc_min 150, so that hand-overs cross between
+  the kernel kinds: per cluster (fused=False) the two outer clusters run on
+  the plain FP32 kernels; with one launch per sub-step (fused=True) the
+  sub-steps that update fewer than 150 elements (cluster 0 alone) run on the
+  plain kernels and the others on the matrix cores.
 * A three-material box (water, sediment, rock: S impedances differ on the
   two sides of the sediment-rock faces) in FP64 and FP32.
 
@@ -123,15 +126,16 @@ def test_lts_four_clusters_fp64_plain(order):
     assert fe.max() <= TOL64_FIELD and ee.max() <= TOL64_ELEM and eta <= TOL64_FIELD
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("mc_min", [0, 150])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("order", [5, 6, 7])
-def test_lts_four_clusters_tuned(order, precision, mc_min):
+def test_lts_four_clusters_tuned(order, precision, mc_min, fused):
     mesh, mats = lts_box()
     ref = oracle_result("lts", lts_box, order, STEPS_REDUCED, 4)
-    say(f"case: lts box order={order} {precision}/tuned mc_min={mc_min} {STEPS_REDUCED} macro steps")
+    say(f"case: lts box order={order} {precision}/tuned mc_min={mc_min} fused={fused} {STEPS_REDUCED} macro steps")
     d, e = gpu_run(mesh, mats, order, STEPS_REDUCED, ref, precision=precision, kernel="tuned", max_clusters=4,
-                   mc_min=mc_min)
+                   mc_min=mc_min, fused=fused)
     fe, ee, eta = errors(d, e, ref)
     say(f"  field {np.array2string(fe, precision=2)} element max {ee.max():.2e} "
         f"median {np.median(ee):.2e} eta {eta:.2e}")
