@@ -870,9 +870,12 @@ constexpr int kCorrAhead = 1;
 // Corrector: Q -= sum_f L_f flux(neighbour trace of face f). The output rows
 // are produced in SPLIT passes (the face fluxes are recomputed per
 // pass from the inbox, which is L2-resident by then) so that the accumulators
-// of one pass leave room for two wavefronts per SIMD.
+// of one pass leave room for two wavefronts per SIMD: the two-pass form is
+// compiled for at most 256 registers up to order 6 (at order 7 that would
+// spill, and it keeps one wavefront per SIMD).
 template <class Op, int N, int W, int SPLIT>
-__global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, int64_t e1, int remap) {
+__global__ __launch_bounds__(64 * W, (SPLIT >= 2 && N <= 5) ? 2 : 1) void k_correct_tuned(TArgs a, int64_t e0, int64_t e1,
+                                                                               int remap) {
   using L = Lay<Op, N>;
   constexpr int B = L::B, Bf = L::Bf, RT = L::RT, FT = L::FT;
   constexpr int NS = (SPLIT > RT) ? RT : SPLIT;
@@ -924,11 +927,11 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
           dst[v][8] = blk[512 + lane];
         }
       };
-      float c[4][11];
+      // flux coefficients of the current face and the next (requested one
+      // step before the next face starts)
+      float c[2][11];
 #pragma unroll
-      for (int f = 0; f < 4; ++f)
-#pragma unroll
-        for (int i = 0; i < 11; ++i) c[f][i] = a.RCp[(ec * 4 + f) * 12 + i];
+      for (int i = 0; i < 11; ++i) c[0][i] = a.RCp[(ec * 4) * 12 + i];
       float tb[CD + 1][4][9];
 #pragma unroll
       for (int s = 0; s < CD; ++s) load_step(s, tb[s]);
@@ -937,12 +940,16 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
       for (int s = 0; s < NSTEP; ++s) {
         const int f = s / FT, t = s % FT;
         if (s + CD < NSTEP) load_step(s + CD, tb[(s + CD) % (CD + 1)]);
+        if (t == FT - 1 && f + 1 < 4) {
+#pragma unroll
+          for (int i = 0; i < 11; ++i) c[(f + 1) & 1][i] = a.RCp[(ec * 4 + f + 1) * 12 + i];
+        }
         float(&cur)[4][9] = tb[s % (CD + 1)];
         float V[4][9];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float out[9];
-          node_flux(c[f], lam, mu, rinv, cur[v], out);
+          node_flux(c[f & 1], lam, mu, rinv, cur[v], out);
           const bool ok = 16 * t + 4 * v + g < Bf;  // node in slot (t, g, v)
 #pragma unroll
           for (int p = 0; p < 9; ++p) V[v][p] = ok ? out[p] : 0.0f;
@@ -956,8 +963,10 @@ __global__ __launch_bounds__(64 * W) void k_correct_tuned(TArgs a, int64_t e0, i
         __builtin_amdgcn_sched_barrier(0);
       }
       // up to four of the pass's row tiles are requested before their stores
-      // (raw buffer accesses may alias): one memory latency per batch
-      constexpr int QB = MH < 4 ? MH : 4;
+      // (raw buffer accesses may alias): one memory latency per batch; one
+      // tile at a time in the two-pass form, whose registers must leave room
+      // for two wavefronts per SIMD
+      constexpr int QB = SPLIT >= 2 ? 1 : (MH < 4 ? MH : 4);
       const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
 #pragma unroll
       for (int u0 = 0; u0 < MH; u0 += QB) {
