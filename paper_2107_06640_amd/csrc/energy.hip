@@ -10,7 +10,7 @@
 // face rule of the eta points (weights summing to 1/2).
 //
 // One wavefront takes one 16-element group (lane el + 16 g holds rows
-// 16 t + 4 g + v of element el, the layout of the state), a work-group of four
+// 16 t + 4 v + g of element el, the layout of the state), a work-group of four
 // wavefronts strides over the groups and then over the gravity faces, and
 // leaves its kEnergyValues sums in a partial-sum buffer; one more work-group
 // adds the partial sums in a fixed order, so the result is reproducible.
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kThreads) void k_energy_partial(EnergyData d, const
     double s2[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, tr2 = 0.0;
     for (int t = 0; t < RT; ++t)
       for (int v = 0; v < 4; ++v) {
-        if (16 * t + 4 * g + v >= d.B) continue;
+        if (16 * t + 4 * v + g >= d.B) continue;
         const T* q = Q + (((grp * RT + t) * 4 + v) * 9) * 64 + lane;
         double x[9];
         for (int p = 0; p < 9; ++p) {

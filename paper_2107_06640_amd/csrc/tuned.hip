@@ -142,21 +142,33 @@ using RefT = typename std::conditional<std::is_same<Op, OpF32>::value, float, un
 // of the FP32 products first. The map is its own inverse.
 __host__ __device__ constexpr int node_of(int c) { return (c & ~15) + 4 * (c & 3) + ((c >> 2) & 3); }
 
+// State row held in fragment row i of a 16-row tile (lane group i / 4, slot
+// i % 4): row 4 (i % 4) + i / 4 of the tile (the state layout runs over the
+// lane groups first, see layout.hpp).
+__device__ __forceinline__ int frag_row(int i) { return tile_perm(i); }
+
+// Rows of the state (the basis index) appear in the image either in their
+// natural order (FP32: the kernels permute their fragment indices instead,
+// see frag_row) or, for BF16, already in fragment order (tile_perm, with every
+// row dimension padded to whole tiles), because a BF16 fragment reads four
+// consecutive K entries at once.
 template <class Op, int N>
 struct Lay {
   static constexpr bool BF = std::is_same<Op, OpBF16>::value;
   static constexpr int B = nbasis(N), Bf = nface(N), B1 = nbasis(N - 1);
   static constexpr int RT = row_tiles(B), FT = row_tiles(Bf), RT1 = row_tiles(B1);
+  static constexpr int PB = BF ? 16 * RT : B;     // extent of a B-row dimension in the image
+  static constexpr int PB1 = BF ? 16 * RT1 : B1;  // extent of a B1-row dimension
   static constexpr int r4(int x) { return BF ? (x + 3) / 4 * 4 : x; }
-  static constexpr int ldK = r4(B1);   // K^d[l < B][m < B1]   (volume: A(k,l) = K[k][l]; FP32 CK: A(m,l) = K[l][m])
-  static constexpr int ldT = r4(B);    // BF16 CK: (K^d)^T[m < B1][l < B]
+  static constexpr int ldK = r4(PB1);  // K^d[l < B][m < B1]   (volume: A(k,l) = K[k][l]; FP32 CK: A(m,l) = K[l][m])
+  static constexpr int ldT = r4(PB);   // BF16 CK: (K^d)^T[m < B1][l < B]
   // face nodes in slot order (see node_of): FT * 16 slots per face
-  static constexpr int ldE = r4(B);       // E_f[slot < 16 FT][row < B]
+  static constexpr int ldE = r4(PB);      // E_f[slot < 16 FT][row < B]
   static constexpr int ldL = 16 * FT;     // L_f[row < B][slot < 16 FT]
-  static constexpr int nK = 3 * B * ldK;
-  static constexpr int nT = BF ? 3 * B1 * ldT : 0;
+  static constexpr int nK = 3 * PB * ldK;
+  static constexpr int nT = BF ? 3 * PB1 * ldT : 0;
   static constexpr int nE = 4 * 16 * FT * ldE;
-  static constexpr int nL = 4 * B * ldL;
+  static constexpr int nL = 4 * PB * ldL;
   static constexpr int maxld = (ldK > ldE ? ldK : ldE) > ldL ? (ldK > ldE ? ldK : ldE) : ldL;
   static constexpr int tail = 16 * (maxld > ldT ? maxld : ldT) + 64;
   // the lift block starts on a 16-byte boundary (the corrector stages it alone)
@@ -219,20 +231,26 @@ constexpr int kPrefetch = 2;
 // keeps the compiler from hoisting every load of the loop (which would need a
 // register per load in flight).
 // NODEK: the K index runs over face nodes in slot order (node 16t + 4v + g in
-// slot (t, g, v)), so a slab (t, v) holds nodes 16t + 4v .. 16t + 4v + 3 and a
-// partial last tile needs only its first slabs.
+// slot (t, g, v)) and the output rows are state rows; otherwise the K index
+// runs over state rows (row 16t + 4v + g in register v of lane group g) and
+// the output rows are face nodes. Either way a slab (t, v) holds K entries
+// 16t + 4v .. 16t + 4v + 3, so a partial last tile needs only its first slabs.
 template <class Op, class V, int NT, int MT, bool PIPE = false, bool NODEK = false, class RowFn>
 __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nrows, int el, int g, RowFn rowfn) {
   if constexpr (std::is_same<Op, OpF32>::value) {
     constexpr int D = PIPE ? kPrefetch : 0;  // rows requested ahead
     float b[D + 1][9];
     float an[2][MT];  // A fragments of this row and the next (read from LDS one row ahead)
-    auto valid = [&](int i) {
-      return i < 4 * NT && 16 * (i >> 2) + (NODEK ? 4 * (i & 3) : (i & 3)) < nrows;
-    };
+    // slab (t, v) holds rows (or nodes) 16t + 4v .. 16t + 4v + 3
+    auto valid = [&](int i) { return i < 4 * NT && 16 * (i >> 2) + 4 * (i & 3) < nrows; };
+    // FP32 images keep state rows in natural order: a fragment row (M side)
+    // that is a state row is frag_row(el), a K index that is a state row is
+    // 16t + 4v + g; node slots are stored in fragment order already
+    const int mrow = NODEK ? frag_row(el) : el;
     auto load_a = [&](int i, float(&dst)[MT]) {
+      const int k = NODEK ? 16 * (i >> 2) + 4 * g + (i & 3) : 16 * (i >> 2) + 4 * (i & 3) + g;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) dst[mt] = A.at(16 * mt + el, 16 * (i >> 2) + 4 * g + (i & 3));
+      for (int mt = 0; mt < MT; ++mt) dst[mt] = A.at(16 * mt + mrow, k);
     };
 #pragma unroll
     for (int j = 0; j < D; ++j)
@@ -318,7 +336,7 @@ __device__ __forceinline__ void store_deriv(float* dst, const float (&x)[RTX][4]
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = 16 * t + 4 * g + v;
+      const int row = 16 * t + 4 * v + g;
       if (row >= B) continue;
 #pragma unroll
       for (int p = 0; p < 9; ++p) dst[row * 9 + p] = (t < RTX) ? x[t < RTX ? t : 0][v][p] : 0.0f;
@@ -343,15 +361,16 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
   if constexpr (std::is_same<Op, OpF32>::value) {
     // slabs (d, row) in order; the K^d fragments of the next slab are read from
     // LDS while the products of the current one run
-    const View<float, L::ldK, true> A0(lds + L::oK), A1(lds + L::oK + L::B * L::ldK),
-        A2(lds + L::oK + 2 * L::B * L::ldK);  // A(m, l) = K^d[l][m]
-    constexpr int NV = (nin / 16) * 4 + ((nin % 16) < 4 ? (nin % 16) : 4);  // rows (t, v) with 16t + v < nin
+    const View<float, L::ldK, true> A0(lds + L::oK), A1(lds + L::oK + L::PB * L::ldK),
+        A2(lds + L::oK + 2 * L::PB * L::ldK);  // A(m, l) = K^d[l][m]
+    constexpr int NV = (nin / 16) * 4 + ((nin % 16) + 3) / 4;  // slabs (t, v) with 16t + 4v < nin
+    const int mrow = frag_row(el);
     float an[2][RTO];
     auto load_a = [&](int s, float(&dst)[RTO]) {
-      const int d = s / NV, i = s % NV, k = 16 * (i >> 2) + 4 * g + (i & 3);
+      const int d = s / NV, i = s % NV, k = 16 * (i >> 2) + 4 * (i & 3) + g;
 #pragma unroll
       for (int mt = 0; mt < RTO; ++mt)
-        dst[mt] = d == 0 ? A0.at(16 * mt + el, k) : (d == 1 ? A1.at(16 * mt + el, k) : A2.at(16 * mt + el, k));
+        dst[mt] = d == 0 ? A0.at(16 * mt + mrow, k) : (d == 1 ? A1.at(16 * mt + mrow, k) : A2.at(16 * mt + mrow, k));
     };
     if constexpr (N <= 5) {
       // software pipeline over the slabs: while the products of slab s run,
@@ -401,7 +420,7 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     {
-      const View<unsigned short, L::ldT, false> A(lds + L::oT + d * L::B1 * L::ldT);  // (K^d)^T[m][l]
+      const View<unsigned short, L::ldT, false> A(lds + L::oT + d * L::PB1 * L::ldT);  // (K^d)^T[m][l]
 #pragma unroll
       for (int t = 0; t < RTI; ++t) {
         if (16 * t >= nin) continue;
@@ -427,7 +446,7 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
   for (int mt = 0; mt < RTO; ++mt)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int row = 16 * mt + 4 * g + v;
+      const int row = 16 * mt + 4 * v + g;
 #pragma unroll
       for (int p = 0; p < NP; ++p) dout[mt][v][P0 + p] = row < nout ? fk * acc[mt][p][v] : 0.0f;
     }
@@ -457,7 +476,7 @@ __device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * t + 4 * g + v;
+        const int row = 16 * t + 4 * v + g;
         if (row >= B) continue;
 #pragma unroll
         for (int p = C0; p < C1; ++p) gd[row * 9 + p] = din[t][v][p];
@@ -532,22 +551,24 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
   using L = Lay<Op, N>;
   constexpr int B = L::B, B1 = L::B1, RT = L::RT, RT1 = L::RT1;
   using R = RefT<Op>;
-  const View<R, L::ldK, false> A0(lds + L::oK), A1(lds + L::oK + B * L::ldK), A2(lds + L::oK + 2 * B * L::ldK);
+  const View<R, L::ldK, false> A0(lds + L::oK), A1(lds + L::oK + L::PB * L::ldK),
+      A2(lds + L::oK + 2 * L::PB * L::ldK);
   if constexpr (std::is_same<Op, OpF32>::value) {
     constexpr int D = kPrefetch;
     float xb[D + 1][9];
-    auto valid = [&](int i) { return i < 4 * RT1 && 16 * (i >> 2) + (i & 3) < B1; };
+    auto valid = [&](int i) { return i < 4 * RT1 && 16 * (i >> 2) + 4 * (i & 3) < B1; };
+    const int mrow = frag_row(el);
 #pragma unroll
     for (int j = 0; j < D; ++j)
       if (valid(j)) rowfn(j >> 2, j & 3, xb[j % (D + 1)]);
     float an[2][3][RT];  // K^d fragments of this row and the next
     auto load_a = [&](int i, float(&dst)[3][RT]) {
-      const int k = 16 * (i >> 2) + 4 * g + (i & 3);
+      const int k = 16 * (i >> 2) + 4 * (i & 3) + g;
 #pragma unroll
       for (int mt = 0; mt < RT; ++mt) {
-        dst[0][mt] = A0.at(16 * mt + el, k);
-        dst[1][mt] = A1.at(16 * mt + el, k);
-        dst[2][mt] = A2.at(16 * mt + el, k);
+        dst[0][mt] = A0.at(16 * mt + mrow, k);
+        dst[1][mt] = A1.at(16 * mt + mrow, k);
+        dst[2][mt] = A2.at(16 * mt + mrow, k);
       }
     };
     load_a(0, an[0]);
@@ -558,7 +579,7 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
       if (valid(i + D)) rowfn((i + D) >> 2, (i + D) & 3, xb[(i + D) % (D + 1)]);
       if (valid(i + 1)) load_a(i + 1, an[(i + 1) & 1]);
       const float(&x)[9] = xb[i % (D + 1)];
-      const bool ok = 16 * t + 4 * g + v < B1;
+      const bool ok = 16 * t + 4 * v + g < B1;
       float z[3][9];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -595,7 +616,7 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
         float z[4][9];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const bool ok = 16 * t + 4 * g + v < B1;
+          const bool ok = 16 * t + 4 * v + g < B1;
           apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, xb[t & 1][v], z[v]);
 #pragma unroll
           for (int p = 0; p < 9; ++p) z[v][p] = ok ? z[v][p] : 0.0f;
@@ -822,7 +843,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
           for (int p = 0; p < 9; ++p) V[t][v][p] = out[p];
         }
-      const View<R, L::ldL, false> AL(lds + L::oL + f * B * L::ldL);
+      const View<R, L::ldL, false> AL(lds + L::oL + f * L::PB * L::ldL);
       contract_fn<Op, View<R, L::ldL, false>, FT, RT, false, true>(dq, AL, Bf, el, g,
                                                       [&](int t, int v, float (&b)[9]) {
 #pragma unroll
@@ -855,7 +876,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int t = t0 + u;
-            if (t >= RT || !live || 16 * t + 4 * g + v >= B) continue;
+            if (t >= RT || !live || 16 * t + 4 * v + g >= B) continue;
 #pragma unroll
             for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[u][v * 9 + p] + dq[t < RT ? t : 0][p][v]);
           }
@@ -954,7 +975,7 @@ __global__ __launch_bounds__(64 * W, (SPLIT >= 2 && N <= 5) ? 2 : 1) void k_corr
 #pragma unroll
           for (int p = 0; p < 9; ++p) V[v][p] = ok ? out[p] : 0.0f;
         }
-        const View<R, L::ldL, false> AL(ldsL + f * B * L::ldL + t0 * 16 * L::ldL + 16 * t);
+        const View<R, L::ldL, false> AL(ldsL + f * L::PB * L::ldL + t0 * 16 * L::ldL + 16 * t);
         contract_fn<Op, View<R, L::ldL, false>, 1, MH, false, true>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
                                                        [&](int, int v, float (&b)[9]) {
 #pragma unroll
@@ -981,7 +1002,7 @@ __global__ __launch_bounds__(64 * W, (SPLIT >= 2 && N <= 5) ? 2 : 1) void k_corr
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int uu = u0 + u, t = t0 + uu;
-            if (uu >= MH || t >= RT || !live || 16 * t + 4 * g + v >= B) continue;
+            if (uu >= MH || t >= RT || !live || 16 * t + 4 * v + g >= B) continue;
 #pragma unroll
             for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[u][v * 9 + p] + dq[uu < MH ? uu : 0][p][v]);
           }
@@ -1185,20 +1206,22 @@ std::vector<double> ref_image(const Model& M) {
   using L = Lay<Op, N>;
   const int B = L::B, Bf = L::Bf, B1 = L::B1;
   std::vector<double> r(L::total, 0.0);
+  // position of state row k in the image: fragment order for BF16
+  auto pos = [](int k) { return L::BF ? tile_perm(k) : k; };
   for (int d = 0; d < 3; ++d)
     for (int k = 0; k < B; ++k)
       for (int l = 0; l < B1; ++l) {
         const double v = M.ref.K[(d * B + k) * B + l];
-        r[L::oK + (d * B + k) * L::ldK + l] = v;
-        if (L::BF) r[L::oT + (d * B1 + l) * L::ldT + k] = v;
+        r[L::oK + (d * L::PB + pos(k)) * L::ldK + pos(l)] = v;
+        if (L::BF) r[L::oT + (d * L::PB1 + pos(l)) * L::ldT + pos(k)] = v;
       }
   for (int f = 0; f < 4; ++f)
     for (int c = 0; c < 16 * L::FT; ++c) {
       const int m = node_of(c);
       if (m >= Bf) continue;  // padding slot: zero
       for (int k = 0; k < B; ++k) {
-        r[L::oE + (f * 16 * L::FT + c) * L::ldE + k] = M.ref.E[(f * Bf + m) * B + k];
-        r[L::oL + (f * B + k) * L::ldL + c] = M.ref.L[(f * B + k) * Bf + m];
+        r[L::oE + (f * 16 * L::FT + c) * L::ldE + pos(k)] = M.ref.E[(f * Bf + m) * B + k];
+        r[L::oL + (f * L::PB + pos(k)) * L::ldL + c] = M.ref.L[(f * B + k) * Bf + m];
       }
     }
   return r;

@@ -2,7 +2,9 @@
 
 A small host program built from the library's own layout header checks, for
 every order and a ragged element count, that
-* qidx maps (element, row, quantity) one-to-one into [0, q_size);
+* qidx maps (element, row, quantity) one-to-one into [0, q_size), row r of
+  element el in tile r >> 4, slot v = (r >> 2) & 3 and lane el + 16 (r & 3)
+  (rows run over the lane groups first inside a tile);
 * inidx maps (element, face, node, quantity) one-to-one into [0, in_size);
 * the quantities 0..7 of a node are eight consecutive values starting on a
   16-byte boundary (two vector stores), and quantity 8 sits in its block's
@@ -39,6 +41,10 @@ int main() {
         for (int p = 0; p < 9; ++p) {
           const int64_t i = qidx(e, r, p, RT);
           if (i < 0 || i >= (int64_t)seen.size() || seen[i]++) ++bad;
+          // row r in tile r >> 4, slot v = (r >> 2) & 3, lane group g = r & 3
+          const int64_t want = ((((e >> 4) * RT + (r >> 4)) * 4 + ((r >> 2) & 3)) * 9 + p) * 64 + (e & 15) + 16 * (r & 3);
+          if (i != want) ++bad;
+          if (tile_perm(tile_perm(r)) != r || (tile_perm(r) >> 4) != (r >> 4)) ++bad;
         }
     std::vector<int> in(in_size(E, FT), 0);
     for (int64_t e = 0; e < E; ++e)
