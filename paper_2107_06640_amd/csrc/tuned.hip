@@ -159,12 +159,17 @@ struct Lay {
   static constexpr int RT = row_tiles(B), FT = row_tiles(Bf), RT1 = row_tiles(B1);
   static constexpr int PB = BF ? 16 * RT : B;     // extent of a B-row dimension in the image
   static constexpr int PB1 = BF ? 16 * RT1 : B1;  // extent of a B1-row dimension
-  static constexpr int r4(int x) { return BF ? (x + 3) / 4 * 4 : x; }
+  // Leading dimensions. BF16: multiples of 4 entries (a fragment reads four
+  // consecutive K entries as one 8-byte word). FP32: padded so that the 64
+  // lanes of a fragment read (16 rows x 4 K entries) fall on distinct LDS
+  // banks up to pairs; a multiple of 8 (or 16 x FT for the lifts, 8- to
+  // 16-way conflicts) is avoided.
+  static constexpr int r4(int x) { return BF ? (x + 3) / 4 * 4 : x + (x % 8 == 0 ? 1 : 0); }
   static constexpr int ldK = r4(PB1);  // K^d[l < B][m < B1]   (volume: A(k,l) = K[k][l]; FP32 CK: A(m,l) = K[l][m])
   static constexpr int ldT = r4(PB);   // BF16 CK: (K^d)^T[m < B1][l < B]
   // face nodes in slot order (see node_of): FT * 16 slots per face
-  static constexpr int ldE = r4(PB);      // E_f[slot < 16 FT][row < B]
-  static constexpr int ldL = 16 * FT;     // L_f[row < B][slot < 16 FT]
+  static constexpr int ldE = r4(PB);                   // E_f[slot < 16 FT][row < B]
+  static constexpr int ldL = BF ? 16 * FT : 16 * FT + 3;  // L_f[row < B][slot < 16 FT]
   static constexpr int nK = 3 * PB * ldK;
   static constexpr int nT = BF ? 3 * PB1 * ldT : 0;
   static constexpr int nE = 4 * 16 * FT * ldE;
