@@ -215,6 +215,45 @@ int seis_profile(seis_t *h, int enable);
  * be NULL. Synchronises the stream. */
 int seis_profile_read(seis_t *h, double *ms, int64_t *launches, int64_t *elements);
 
+/* Output at points (Sec. 6.2 writes receivers every 0.01 s, and the sea
+ * surface and the elastic-acoustic interface every 0.1 s of simulated time).
+ * A point set is fixed once; seis_sample then evaluates the current state at
+ * its points on the device, so that a time series is one sample after each
+ * macro step of the right length (all clusters are at the same time only
+ * between macro steps). Two sets are built in:
+ *   SEIS_POINTS_SEA_SURFACE: the eta points of every gravity face, in the
+ *     order of the eta array (faces by (element, local face), points by the
+ *     face rule documented above), evaluated in the acoustic element;
+ *   SEIS_POINTS_SEAFLOOR: the same face rule on every elastic-acoustic face,
+ *     evaluated in its elastic element; faces ordered by (caller element of
+ *     the elastic side, local face). */
+enum { SEIS_POINTS_SEA_SURFACE = -1, SEIS_POINTS_SEAFLOOR = -2 };
+
+/* Define a set of n receivers at physical points xyz [n][3] (host, FP64,
+ * copied). Each point is evaluated in the element that contains it (within
+ * 1e-9 in barycentric coordinates); of several (a point on a shared face,
+ * edge or vertex) the one with the lowest caller id. *id receives the set's
+ * id (0, 1, ... in order of definition). Allocates device memory for the
+ * set's basis values (n x B doubles), freed by seis_destroy.
+ * Errors: SEIS_EINVAL (NULL argument, n <= 0, a point outside the mesh). */
+int seis_points(seis_t *h, int64_t n, const double *xyz, int *id);
+
+/* Size of a point set and (each nullable, host) its points [n][3] and the
+ * caller id of the element each point is evaluated in [n]. For a built-in
+ * set the first call builds it (host work and a device allocation).
+ * Errors: SEIS_ERANGE (no such set). */
+int seis_points_info(seis_t *h, int id, int64_t *n, double *xyz, int64_t *element);
+
+/* The nine quantities (order above) at the points of set id from the
+ * current state, out: DEVICE pointer [n][9] FP64, asynchronous on the
+ * handle's stream. eta (DEVICE [n], nullable) receives the sea-surface
+ * height at the points; only for SEIS_POINTS_SEA_SURFACE. Launches one
+ * kernel and allocates nothing once the set exists (a built-in set is built
+ * at its first use: call seis_points_info first when capturing a graph).
+ * Errors: SEIS_EINVAL, SEIS_ERANGE, SEIS_EORDER (between a prediction and its
+ * correction), SEIS_EDEVICE. */
+int seis_sample(seis_t *h, int id, double *out, double *eta);
+
 /* Energy and field norms of the current state (Sec. 3: the velocity-stress
  * system with the gravitational sea surface, whose energy
  *   E = sum_K int_K (rho |v|^2 / 2 + W(s)) + int_surface rho g eta^2 / 2

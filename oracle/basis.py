@@ -90,6 +90,50 @@ def eval_basis(N: int, pts) -> np.ndarray:
     return np.stack(cols, axis=1)
 
 
+def jacobi_h(n: int, alpha: float, beta: float, num, den):
+    """den^n P_n^(alpha,beta)(num / den), a polynomial in (num, den).
+
+    The recurrence of ``jacobi`` multiplied through by den^(k+1); finite where
+    den = 0, which is where the collapsed coordinates are singular.
+    """
+    num = np.asarray(num, dtype=np.float64)
+    den = np.asarray(den, dtype=np.float64)
+    h0 = np.ones_like(num)
+    if n == 0:
+        return h0
+    h1 = 0.5 * (alpha - beta) * den + 0.5 * (alpha + beta + 2.0) * num
+    for k in range(1, n):
+        a1 = 2.0 * (k + 1) * (k + alpha + beta + 1) * (2 * k + alpha + beta)
+        a2 = (2 * k + alpha + beta + 1) * (alpha * alpha - beta * beta)
+        a3 = (2 * k + alpha + beta) * (2 * k + alpha + beta + 1) * (2 * k + alpha + beta + 2)
+        a4 = 2.0 * (k + alpha) * (k + beta) * (2 * k + alpha + beta + 2)
+        h0, h1 = h1, ((a2 * den + a3 * num) * h1 - a4 * den * den * h0) / a1
+    return h1
+
+
+def eval_basis_closed(N: int, pts) -> np.ndarray:
+    """phi_l at points of the closed reference tetrahedron [n, 3] -> [n, B].
+
+    The same functions as ``eval_basis``, written without the division of the
+    collapsed coordinates: with a = num_a / den_a, num_a = 2x - (1-y-z),
+    den_a = 1-y-z and b = num_b / den_b, num_b = 2y - (1-z), den_b = 1-z,
+    the factors ((1-b)/2)^p ((1-c)/2)^(p+q) equal den_a^p den_b^q, so
+    phi_pqr = [den_a^p P_p(a)] [den_b^q P_q^(2p+1,0)(b)] P_r^(2p+2q+2,0)(c),
+    which holds on the faces, edges and vertices as well (receivers there).
+    """
+    pts = np.asarray(pts, dtype=np.float64)
+    x, y, z = pts[:, 0], pts[:, 1], pts[:, 2]
+    da, db = 1.0 - y - z, 1.0 - z
+    na, nb_ = 2.0 * x - da, 2.0 * y - db
+    c = 2.0 * z - 1.0
+    cols = []
+    for (p, q, r) in basis_indices(N):
+        v = (jacobi_h(p, 0.0, 0.0, na, da) * jacobi_h(q, 2.0 * p + 1.0, 0.0, nb_, db)
+             * jacobi(r, 2.0 * p + 2.0 * q + 2.0, 0.0, c))
+        cols.append(v / math.sqrt(norm2(p, q, r)))
+    return np.stack(cols, axis=1)
+
+
 _H = 1.0e-30
 
 

@@ -335,6 +335,56 @@ class Oracle:
         qv = ein("qb,ebp->eqp", self.phi_v, Q)
         return ein("e,q,eqp->p", self.geo.absdet, self.vw, qv ** 2)
 
+    # ------------------------------------------------------------------
+    # output at points: receivers, the sea surface and the seafloor (Sec. 6.2)
+    def locate(self, points, tol=1e-9):
+        """Element and reference coordinates of physical points [n, 3].
+
+        A point belongs to the elements whose barycentric coordinates are all
+        >= -tol; of several (a point on a shared face, edge or vertex) the one
+        with the lowest element id is taken. Raises if a point is outside.
+        """
+        points = np.atleast_2d(np.asarray(points, dtype=np.float64))
+        elem = np.empty(points.shape[0], dtype=np.int64)
+        xi = np.empty((points.shape[0], 3))
+        for k, x in enumerate(points):
+            ref = np.einsum("edc,ec->ed", self.geo.Jinv, x[None, :] - self.geo.x0)
+            bary = np.concatenate([1.0 - ref.sum(axis=1, keepdims=True), ref], axis=1)
+            inside = np.nonzero(np.all(bary >= -tol, axis=1))[0]
+            if inside.size == 0:
+                raise ValueError(f"point {x} is outside the mesh")
+            elem[k] = inside[0]
+            xi[k] = ref[inside[0]]
+        return elem, xi
+
+    def sample(self, points, Q=None):
+        """The nine quantities at physical points [n, 3] -> [n, 9] (see locate)."""
+        Q = self.Q if Q is None else Q
+        elem, xi = self.locate(points)
+        phi = bas.eval_basis_closed(self.N, xi)
+        return ein("nb,nbp->np", phi, Q[elem])
+
+    def seafloor_faces(self):
+        """Elastic-acoustic interface faces seen from the elastic side, sorted by (element, face)."""
+        el, fa = [], []
+        for e in range(self.E):
+            if self.mu[e] == 0.0:
+                continue
+            for f in range(4):
+                j = self.nb[e, f]
+                if j >= 0 and self.mu[j] == 0.0:
+                    el.append(e)
+                    fa.append(f)
+        return np.array(el, dtype=np.int64), np.array(fa, dtype=np.int64)
+
+    def face_sample(self, elems, faces, Q=None):
+        """The nine quantities of elements elems at the eta-rule points of their faces -> [n, q, 9]."""
+        Q = self.Q if Q is None else Q
+        out = np.empty((len(elems), self.gst.shape[0], 9))
+        for k, (e, f) in enumerate(zip(elems, faces)):
+            out[k] = self.phi_g[f] @ Q[e]
+        return out
+
     def evaluate(self, x_elem, xi):
         """Solution at reference points xi[n, 3] of elements x_elem[n] -> [n, 9]."""
         phi = bas.eval_basis(self.N, xi)

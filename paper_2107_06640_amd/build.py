@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libseis.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["refelem.cpp", "setup.cpp", "assemble.hip", "abi.hip", "kernels_plain.hip", "tuned.hip", "fno.hip", "energy.hip"]
+SOURCES = ["refelem.cpp", "setup.cpp", "assemble.hip", "abi.hip", "kernels_plain.hip", "tuned.hip", "fno.hip", "energy.hip",
+           "probe.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -15,6 +15,7 @@
 #include "energy.hpp"
 #include "layout.hpp"
 #include "model.hpp"
+#include "probe.hpp"
 #include "tuned.hpp"
 
 using namespace seis;
@@ -77,6 +78,11 @@ struct seis_t {
   // (allocated at its first call)
   EnergyData en{};
   double* en_partial = nullptr;
+  // output point sets: seis_points (ids 0, 1, ...), and the sea surface and
+  // the seafloor (built at their first use)
+  std::vector<PointSet> psets;
+  PointSet sea_set, floor_set;
+  bool sea_built = false, floor_built = false;
   // seis_step launches one kernel per phase per sub-step over every due
   // cluster (options.fused), else one per cluster
   bool fused = true;
@@ -795,6 +801,84 @@ int seis_profile_read(seis_t* h, double* ms, int64_t* launches, int64_t* element
     if (launches) launches[k] = h->tot_launch[k];
     if (elements) elements[k] = h->tot_elem[k];
   }
+  return SEIS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int make_points(seis_t* h, int which, int64_t n, const double* xyz, PointSet& ps) {
+  std::vector<double> phi;
+  std::vector<int32_t> el;
+  std::string e;
+  try {
+    e = build_points(h->M, which, n, xyz, ps, phi, el);
+  } catch (const std::bad_alloc&) {
+    return fail(h, SEIS_ENOMEM, "host allocation failed while locating points");
+  }
+  if (!e.empty()) return fail(h, SEIS_EINVAL, e);
+  HIPCHK(h, upload(h->buf, &ps.phi, phi), "upload point basis values");
+  HIPCHK(h, upload(h->buf, &ps.elem, el), "upload point elements");
+  return SEIS_OK;
+}
+
+// the point set of id (building a built-in set at its first use), or null
+PointSet* point_set(seis_t* h, int id, int* rc) {
+  *rc = SEIS_OK;
+  if (id == SEIS_POINTS_SEA_SURFACE || id == SEIS_POINTS_SEAFLOOR) {
+    const bool sea = id == SEIS_POINTS_SEA_SURFACE;
+    PointSet& ps = sea ? h->sea_set : h->floor_set;
+    bool& built = sea ? h->sea_built : h->floor_built;
+    if (!built) {
+      *rc = make_points(h, sea ? 1 : 2, 0, nullptr, ps);
+      if (*rc != SEIS_OK) return nullptr;
+      built = true;
+    }
+    return &ps;
+  }
+  if (id < 0 || id >= (int)h->psets.size()) {
+    *rc = fail(h, SEIS_ERANGE, "no such point set");
+    return nullptr;
+  }
+  return &h->psets[id];
+}
+
+}  // namespace
+
+extern "C" {
+
+int seis_points(seis_t* h, int64_t n, const double* xyz, int* id) {
+  if (!h || n <= 0 || !xyz || !id) return SEIS_EINVAL;
+  PointSet ps;
+  const int rc = make_points(h, 0, n, xyz, ps);
+  if (rc != SEIS_OK) return rc;
+  h->psets.push_back(std::move(ps));
+  *id = (int)h->psets.size() - 1;
+  return SEIS_OK;
+}
+
+int seis_points_info(seis_t* h, int id, int64_t* n, double* xyz, int64_t* element) {
+  if (!h) return SEIS_EINVAL;
+  int rc = SEIS_OK;
+  PointSet* ps = point_set(h, id, &rc);
+  if (!ps) return rc;
+  if (n) *n = ps->n;
+  if (xyz && ps->n) std::memcpy(xyz, ps->xyz.data(), sizeof(double) * 3 * ps->n);
+  if (element && ps->n) std::memcpy(element, ps->elem_caller.data(), sizeof(int64_t) * ps->n);
+  return SEIS_OK;
+}
+
+int seis_sample(seis_t* h, int id, double* out, double* eta) {
+  if (!h || !out) return SEIS_EINVAL;
+  if (mid_step(h)) return fail(h, SEIS_EORDER, "state is between a prediction and its correction");
+  int rc = SEIS_OK;
+  PointSet* ps = point_set(h, id, &rc);
+  if (!ps) return rc;
+  if (eta && !ps->sea) return fail(h, SEIS_EINVAL, "eta is only sampled on the sea-surface point set");
+  const double* q64 = h->precision == SEIS_FP64 ? h->d64.Q : nullptr;
+  const float* q32 = h->precision == SEIS_FP64 ? nullptr : h->d32.Q;
+  HIPCHK(h, launch_sample(*ps, h->M.B, q64, q32, h->d64.eta, out, eta, h->stream), "sample launch");
   return SEIS_OK;
 }
 

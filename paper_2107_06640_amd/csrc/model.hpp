@@ -66,6 +66,14 @@ struct Model {
   std::vector<int64_t> h2_start;       // [C+1]
   double g = 9.81;
 
+  // the mesh as given (caller order), kept for locating output points
+  std::vector<double> xyz;             // [nv][3]
+  std::vector<int64_t> tet;            // [E][4]
+  // elastic-acoustic interface faces seen from the elastic side, ordered by
+  // (caller element, local face); element ids in library order
+  std::vector<int64_t> floor_elem;
+  std::vector<int8_t> floor_face;
+
   RefElement ref;
 };
 

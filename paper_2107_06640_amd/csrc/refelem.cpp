@@ -142,14 +142,14 @@ void triangle_basis(int N, double s, double t, std::vector<double>& out) {
 const double REF_V[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
 const int FACE_V[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
 
+}  // namespace
+
 void face_to_ref(int i, double s, double t, double xi[3]) {
   const double* a = REF_V[FACE_V[i][0]];
   const double* b = REF_V[FACE_V[i][1]];
   const double* c = REF_V[FACE_V[i][2]];
   for (int d = 0; d < 3; ++d) xi[d] = a[d] + s * (b[d] - a[d]) + t * (c[d] - a[d]);
 }
-
-}  // namespace
 
 int n_basis(int N) { return (N + 1) * (N + 2) * (N + 3) / 6; }
 int n_face_nodes(int N) { return (N + 1) * (N + 2) / 2; }

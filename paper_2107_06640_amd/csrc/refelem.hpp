@@ -50,6 +50,10 @@ void gauss_jacobi(int n, double alpha, double beta, std::vector<double>& x, std:
 // layout [B][3]) at a point of the closed reference tetrahedron.
 void dubiner(int N, const double xi[3], double* val, double* grad);
 
+// Reference coordinates of the point (s, t) of face i (opposite vertex i,
+// parametrised by its other vertices in ascending order).
+void face_to_ref(int i, double s, double t, double xi[3]);
+
 // Index of the vertex map sigma (as in RefElement::sigma), or -1.
 int vertex_map_index(const RefElement& r, const int sigma[3]);
 

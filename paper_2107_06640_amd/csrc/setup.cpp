@@ -365,6 +365,19 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
         for (int p = 0; p < 8; ++p) M.g_par.push_back(par[p]);
         M.g_coef.push_back(rho[e] * g * area[id]);
       }
+  // ---- elastic-acoustic interface faces (elastic side), for output
+  for (int64_t e = 0; e < E; ++e) {
+    if (!(mu[e] > 0.0)) continue;
+    for (int f = 0; f < 4; ++f) {
+      const int64_t id = e * 4 + f;
+      if (nb[id] >= 0 && mu[nb[id] / 4] == 0.0) {
+        M.floor_elem.push_back(M.new_of_old[e]);
+        M.floor_face.push_back(int8_t(f));
+      }
+    }
+  }
+  M.xyz.assign(xyz, xyz + nv * 3);
+  M.tet.assign(tet, tet + E * 4);
   M.g_order.resize(M.g_elem.size());
   std::iota(M.g_order.begin(), M.g_order.end(), 0);
 

@@ -23,7 +23,8 @@ ERRORS = {-1: "SEIS_EINVAL", -2: "SEIS_ENOMEM", -3: "SEIS_EDEVICE", -4: "SEIS_EO
 EXPORTED = ["seis_default_options", "seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step",
             "seis_run", "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
             "seis_destroy", "seis_last_error", "seis_profile", "seis_profile_read", "seis_energy",
-            "seis_energy_noalloc"]
+            "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample"]
+SEIS_POINTS_SEA_SURFACE, SEIS_POINTS_SEAFLOOR = -1, -2
 
 
 class SeisError(RuntimeError):
@@ -96,6 +97,9 @@ def load_library(path: str = LIB_PATH):
     lib.seis_profile.argtypes = [P, C.c_int]
     lib.seis_profile_read.argtypes = [P, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.seis_energy.argtypes = [P, C.c_void_p]
+    lib.seis_points.argtypes = [P, C.c_int64, dp, C.POINTER(C.c_int)]
+    lib.seis_points_info.argtypes = [P, C.c_int, C.POINTER(C.c_int64), dp, C.POINTER(C.c_int64)]
+    lib.seis_sample.argtypes = [P, C.c_int, C.c_void_p, C.c_void_p]
     lib.seis_energy_noalloc.argtypes = [P, C.c_void_p]
     lib.seis_destroy.argtypes = [P]
     lib.seis_destroy.restype = None
@@ -103,7 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.seis_last_error.restype = C.c_char_p
     for name in ("seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step", "seis_run",
                  "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
-                 "seis_profile", "seis_profile_read", "seis_energy", "seis_energy_noalloc"):
+                 "seis_profile", "seis_profile_read", "seis_energy", "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -227,6 +231,27 @@ class Solver:
         """Energy and field norms into 12 doubles at device address ``out_ptr`` (asynchronous)."""
         fn = self._lib.seis_energy_noalloc if noalloc else self._lib.seis_energy
         self._check(fn(self._h, C.c_void_p(int(out_ptr))))
+
+    def points(self, xyz):
+        """Define receivers at physical points [n, 3]; returns the set id."""
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        i = C.c_int()
+        self._check(self._lib.seis_points(self._h, x.shape[0], _ptr(x, C.c_double), C.byref(i)))
+        return i.value
+
+    def points_info(self, set_id):
+        """(points [n, 3], caller element ids [n]) of a point set."""
+        n = C.c_int64()
+        self._check(self._lib.seis_points_info(self._h, int(set_id), C.byref(n), None, None))
+        x = np.empty((n.value, 3))
+        e = np.empty(n.value, dtype=np.int64)
+        self._check(self._lib.seis_points_info(self._h, int(set_id), None, _ptr(x, C.c_double), _ptr(e, C.c_int64)))
+        return x, e
+
+    def sample_into(self, set_id, out_ptr, eta_ptr=None):
+        """The nine quantities at a set's points into device memory [n][9] (asynchronous)."""
+        self._check(self._lib.seis_sample(self._h, int(set_id), C.c_void_p(int(out_ptr)),
+                                          None if eta_ptr is None else C.c_void_p(int(eta_ptr))))
 
     def info(self):
         inf = Info_t()

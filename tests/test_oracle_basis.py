@@ -179,3 +179,24 @@ def test_acoustic_embedding_pressure_wave():
     # p = Z f, v_x = f travelling in +x: state (-p,-p,-p,0,0,0,1,0,0)
     r = np.array([-rho * c] * 3 + [0, 0, 0, 1, 0, 0])
     np.testing.assert_allclose(Jx @ r, c * r, rtol=1e-12)
+
+
+def test_closed_form_equals_the_definition_inside_and_is_exact_at_vertices():
+    """eval_basis_closed equals the collapsed-coordinate definition at interior
+    points, and at the vertices and edge midpoints (where the collapsed
+    coordinates are singular) it reproduces a projected polynomial exactly."""
+    from oracle import basis as bas
+    rng = np.random.default_rng(2)
+    for N in range(1, 7):
+        p = rng.dirichlet(np.ones(4), size=30)[:, 1:]
+        np.testing.assert_allclose(bas.eval_basis_closed(N, p), bas.eval_basis(N, p), rtol=1e-11, atol=1e-11)
+    N = 4
+    q, w = quadrature.tet_rule(N + 2)
+    coef = rng.standard_normal(len(bas.basis_indices(N)))
+    mono = [(a, b, c) for a in range(N + 1) for b in range(N + 1) for c in range(N + 1) if a + b + c <= N]
+    mc = rng.standard_normal(len(mono))
+    f = lambda x: sum(m * x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** c for m, (a, b, c) in zip(mc, mono))
+    dofs = (w[:, None] * bas.eval_basis(N, q) * f(q)[:, None]).sum(axis=0)
+    special = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0.5, 0.5, 0], [0, 0.5, 0.5], [0.5, 0, 0.5],
+                        [0, 0, 0.5], [0, 0.3, 0.7]])
+    np.testing.assert_allclose(bas.eval_basis_closed(N, special) @ dofs, f(special), rtol=1e-10, atol=1e-10)

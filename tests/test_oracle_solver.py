@@ -352,3 +352,54 @@ def test_field_norms_equal_coefficient_norms():
     o.Q[:] = inputs.random_dofs(mesh.n_elements, o.B, seed=3)
     direct = np.einsum("e,ebp->p", o.geo.absdet, o.Q ** 2)
     np.testing.assert_allclose(o.field_sq_norms(), direct, rtol=1e-12)
+
+
+def test_locate_finds_the_kuhn_tetrahedron_of_a_point():
+    """A point of cube (i, j, k) of a box of unit Kuhn cubes lies in the tetrahedron
+    0 -> e_a -> e_a + e_b -> 7 whose axis order (a, b, c) sorts its fractional
+    coordinates decreasingly (closed form of the box numbering)."""
+    mesh = inputs.box_mesh(3, 2, 2, lengths=(3.0, 2.0, 2.0))
+    o = _oracle(mesh, inputs.uniform_materials(mesh, 2700.0, 6000.0, 3464.0), 2)
+    rng = np.random.default_rng(4)
+    pts = rng.uniform([0, 0, 0], [3, 2, 2], size=(40, 3))
+    elem, xi = o.locate(pts)
+    perms = list(itertools.permutations(range(3)))
+    for x, e, r in zip(pts, elem, xi):
+        i, j, k = np.floor(x).astype(int)
+        frac = x - np.floor(x)
+        order = tuple(int(a) for a in np.argsort(-frac))
+        assert e == ((i * 2 + j) * 2 + k) * 6 + perms.index(order)
+        np.testing.assert_allclose(o.geo.x0[e] + o.geo.J[e] @ r, x, atol=1e-12)
+
+
+def test_sample_reproduces_projected_polynomials():
+    """A degree-N polynomial field is represented exactly, so sampling its
+    projection at any point returns the polynomial's value there."""
+    mesh = inputs.box_mesh(2, 2, 2, lengths=(2.0, 2.0, 2.0), jitter=0.15, seed=3)
+    N = 3
+    o = _oracle(mesh, inputs.uniform_materials(mesh, 2700.0, 6000.0, 3464.0), N)
+    rng = np.random.default_rng(6)
+    coef = {m: rng.standard_normal(9) for m in _monomials(N)}
+
+    def fn(x):
+        out = np.zeros((x.shape[0], 9))
+        for (a, b, c), v in coef.items():
+            out += (x[:, 0] ** a * x[:, 1] ** b * x[:, 2] ** c)[:, None] * v[None, :]
+        return out
+
+    o.Q[:] = o.project(fn)
+    pts = rng.uniform(0.05, 1.95, size=(25, 3))
+    np.testing.assert_allclose(o.sample(pts), fn(pts), rtol=1e-10, atol=1e-10)
+
+
+def test_seafloor_faces_are_the_horizontal_interface():
+    """An nx x ny layered box has 2 nx ny triangles on its seafloor, all with
+    the elastic element below (outward normal +z) at the seafloor depth."""
+    mesh, mats = inputs.coupled_box(3, 2, 4, cell=500.0, water_layers=1)
+    o = _oracle(mesh, mats, 2)
+    el, fa = o.seafloor_faces()
+    assert el.size == 2 * 3 * 2
+    np.testing.assert_allclose(o.geo.normal[el, fa], np.tile([0.0, 0.0, 1.0], (el.size, 1)), atol=1e-12)
+    pts = o.geo.face_points(el, fa, o.gst)
+    np.testing.assert_allclose(pts[..., 2], mesh.info["z_seafloor"], atol=1e-9)
+    assert np.all(o.mu[el] > 0)
