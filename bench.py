@@ -379,6 +379,9 @@ def main():
                    "launches_per_step": {k: v[1] / args.steps for k, v in prof.items()},
                    "launch": {"predict": inf["launch"][:3], "correct": inf["launch"][3:7],
                               "mc_min": inf["launch"][7],
+                              "predict_shape": {("fp32", 0): "I~ park LDS", ("fp32", 1): "I~ park HBM",
+                                                ("bf16", 0): "bf16 16x16x16", ("bf16", 1): "bf16 16x16x32"}.get(
+                                                    (args.precision, inf["shape"]), "plain"),
                               "source": ["default", "measured", "cache"][inf["launch_source"]]},
                    "updates_per_step": inf["updates_per_macro_step"]},
         "roofline": roof,

@@ -95,12 +95,13 @@ typedef struct {
   int max_clusters; /* rate-2 LTS clusters (Sec. 4.4); 1 = global time stepping */
   void *stream;     /* hipStream_t to launch on; NULL = the default stream */
   int tile;         /* elements per work-group for the tuned kernels (32: 2 wavefronts, 64: 4);
-                       0 = autotuned: at set-up the launch configurations of the matrix-core
-                       predictor and corrector are timed on the largest cluster and the fastest
-                       kept, cached per (device, order, precision, size class) in the file
-                       $SEIS_TUNE_CACHE (default $HOME/.cache/seis/tune.txt). SEIS_TUNE=0 in the
-                       environment disables tuning; SEIS_TUNE=w,cap,remap,w,cap,remap[,split]
-                       fixes it. */
+                       0 = autotuned: at set-up the launch configurations and the predictor's
+                       shape (FP32: I~ parked in LDS or in HBM; BF16: 16x16x16 or 16x16x32
+                       matrix-core products) are timed on the largest cluster and the fastest
+                       kept, cached per (kernel sources, device, order, precision, size class)
+                       in the file $SEIS_TUNE_CACHE (default $HOME/.cache/seis/tune.txt).
+                       SEIS_TUNE=0 in the environment disables tuning;
+                       SEIS_TUNE=w,cap,remap,w,cap,remap[,split[,shape]] fixes it. */
   int graph;        /* nonzero: seis_step captures its macro step into a hipGraph at its first
                        call and replays that graph afterwards (one launch per macro step) */
   int mc_min;       /* tuned kernels, FP32/BF16: a cluster with fewer elements than this runs on
@@ -138,6 +139,8 @@ typedef struct {
   int launch_source;    /* 0 default or fixed (options.tile, SEIS_TUNE), 1 measured at set-up,
                            2 read from the tuning cache */
   int fused;            /* options.fused */
+  int shape;            /* the predictor's shape: FP32 0 = I~ parked in LDS as far as it fits,
+                           1 = in HBM; BF16 0 = 16x16x16 products, 1 = 16x16x32 products */
 } seis_info_t;
 
 /* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream,

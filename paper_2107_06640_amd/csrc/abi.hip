@@ -770,6 +770,7 @@ int seis_info(const seis_t* h, seis_info_t* info) {
   info->launch[7] = h->tuned.mc_min;
   info->launch_source = h->tuned.source;
   info->fused = h->fused ? 1 : 0;
+  info->shape = h->tuned.pc.variant;
   return SEIS_OK;
 }
 

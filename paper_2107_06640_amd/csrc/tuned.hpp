@@ -42,6 +42,8 @@ struct LaunchCfg {
   int cap = 0;    // work-groups per compute unit of a persistent grid; 0 = one work-group per 16*waves elements
   int remap = 0;  // 1: XCD-contiguous work-group order
   int split = 2;  // corrector: passes over the output rows (1 or 2)
+  int variant = 0;  // predictor shape: FP32 0 = I~ parked in LDS as far as it fits, 1 = in HBM;
+                    // BF16 0 = 16x16x16 products, 1 = 16x16x32 products over two row tiles
 };
 
 struct TunedData {
@@ -57,6 +59,14 @@ struct TunedData {
   DevData<double> d64{};
   DevData<float> d32{};
 };
+
+// Matrix-core launches of one precision (tuned_f32.hip, tuned_bf16.hip).
+hipError_t pred_dispatch_f32(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, const Sched& sc,
+                             hipStream_t s);
+hipError_t pred_dispatch_bf16(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, const Sched& sc,
+                              hipStream_t s);
+hipError_t corr_dispatch_f32(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s);
+hipError_t corr_dispatch_bf16(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s);
 
 hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevData<double>& d64,
                        const DevData<float>& d32, int tile, std::vector<void*>& owned, int64_t& bytes);

@@ -55,7 +55,7 @@ class Info_t(C.Structure):
                 ("n_elements", C.c_int64), ("n_gravity_faces", C.c_int64), ("dt_min", C.c_double),
                 ("time", C.c_double), ("cluster_size", C.c_int64 * 16), ("updates_per_macro_step", C.c_int64),
                 ("device_bytes", C.c_int64), ("launch", C.c_int * 8), ("launch_source", C.c_int),
-                ("fused", C.c_int)]
+                ("fused", C.c_int), ("shape", C.c_int)]
 
 
 _lib = None
