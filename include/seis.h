@@ -61,7 +61,9 @@ enum {
   SEIS_FACE_GRAVITY = 2,   /* sea surface z = 0 with gravity (Sec. 4.3); acoustic elements only */
   SEIS_FACE_ABSORBING = 3, /* zero ghost state */
   SEIS_FACE_WALL = 4,      /* rigid wall: ghost v+ = -v-, same stress */
-  SEIS_FACE_FREE = 5       /* traction-free surface (g = 0): ghost s+ = -s-, same velocity */
+  SEIS_FACE_FREE = 5,      /* traction-free surface (g = 0): ghost s+ = -s-, same velocity */
+  SEIS_FACE_VELOCITY = 6   /* prescribed velocity v_b = (0, 0, du/dt) of the uplift history set by
+                              seis_set_uplift: ghost v+ = 2 v_b - v-, same stress */
 };
 
 enum { SEIS_FP64 = 0, SEIS_FP32 = 1, SEIS_BF16 = 2 };
@@ -161,8 +163,20 @@ int seis_setup(const seis_mesh_t *mesh, const seis_materials_t *mat, int order,
 
 /* Copy state from host FP64: dofs [E][B][9] (caller order) and/or eta
  * [F_g][(N+1)^2]; either may be NULL to keep the current value. Resets the
- * schedule to the start of a macro step. */
+ * schedule to the start of a macro step and the simulated time to 0. */
 int seis_write(seis_t *h, const double *dofs, const double *eta);
+
+/* Uplift history driving the SEIS_FACE_VELOCITY faces (a seafloor uplift,
+ * the input of a one-way linked tsunami model, Sec. 2; here prescribed at the
+ * bottom of the solid): n <= 16 sources src [n][5] = (A [m], x_c, y_c [m],
+ * w [m] > 0, T [s] > 0),
+ *   u(x, y, t) = sum_j A_j exp(-((x - x_j)^2 + (y - y_j)^2) / (2 w_j^2)) S(t / T_j),
+ *   S(s) = 0 for s <= 0, s - sin(2 pi s)/(2 pi) for 0 < s < 1, 1 for s >= 1,
+ * with t the simulated time since the last seis_write. The faces impose the
+ * velocity (0, 0, du/dt) weakly through the ghost state; over an element's
+ * step the ghost contributes the exact time integral 2 (u(t1) - u(t0)).
+ * Synchronises the stream; n = 0 removes the forcing. Errors: SEIS_EINVAL. */
+int seis_set_uplift(seis_t *h, int n, const double *src);
 
 /* ADER predictor of every element of cluster c for its next step (Sec. 4.1,
  * Taylor expansion; Cauchy-Kowalevski procedure), its time integral, the

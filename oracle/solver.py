@@ -39,7 +39,22 @@ from .mesh import Geometry, adjacency, ref_face_points, FACE_VERTS
 from .physics import jacobians, stress_tensor
 from .riemann import godunov_flux, ghost_state, gravity_eta_step, flux_of_state
 
-FACE_INTERIOR, FACE_PERIODIC, FACE_GRAVITY, FACE_ABSORBING, FACE_WALL, FACE_FREE = range(6)
+FACE_INTERIOR, FACE_PERIODIC, FACE_GRAVITY, FACE_ABSORBING, FACE_WALL, FACE_FREE, FACE_VELOCITY = range(7)
+
+
+def uplift(sources, x, y, t):
+    """Seafloor uplift u(x, y, t) = sum_j A_j exp(-r_j^2 / (2 w_j^2)) S(t / T_j).
+
+    S rises from 0 to 1 over the rise time: S(s) = s - sin(2 pi s) / (2 pi) on
+    [0, 1] (zero slope at both ends), 0 before and 1 after. The bottom of the
+    solid moves with velocity (0, 0, du/dt) (prescribed-velocity faces).
+    """
+    u = np.zeros(np.broadcast(x, y).shape)
+    for a, cx, cy, w, T in sources:
+        s = np.clip(t / T, 0.0, 1.0)
+        ramp = s - np.sin(2.0 * np.pi * s) / (2.0 * np.pi)
+        u = u + a * np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2.0 * w * w)) * ramp
+    return u
 
 # tensor contractions written as einsum; 'optimize' lets numpy pair them through BLAS
 ein = functools.partial(np.einsum, optimize=True)
@@ -100,6 +115,10 @@ class Oracle:
         self.phi_f = [bas.eval_basis(N, ref_face_points(i, self.fst)) for i in range(4)]
         self.gst, self.gw = quad.tri_rule(N + 1)
         self.phi_g = [bas.eval_basis(N, ref_face_points(i, self.gst)) for i in range(4)]
+        # the uplift forcing of prescribed-velocity faces is not polynomial on
+        # a face: its face integrals use a rule of N + 10 points per direction
+        self.hst, self.hw = quad.tri_rule(N + 10)
+        self.phi_h = [bas.eval_basis(N, ref_face_points(i, self.hst)) for i in range(4)]
 
         # time steps and clusters (Sec. 4.4)
         self.dt_elem = cfl / (2 * N + 1) * self.geo.h / self.cp
@@ -125,6 +144,7 @@ class Oracle:
         self.eta = np.zeros((ge.size, self.gst.shape[0]))
 
         self.Q = np.zeros((E, self.B, 9))
+        self.uplift_sources = []
         self._nb_cache = {}
         self.time = 0.0
         self.updates = 0
@@ -226,6 +246,12 @@ class Oracle:
                 sel = np.nonzero(kind == k)[0]
                 if sel.size:
                     Ip[sel] = ghost_state(k, Im[sel])
+            vel = np.nonzero(kind == FACE_VELOCITY)[0]
+            if vel.size:
+                # prescribed velocity v_b = (0, 0, du/dt): ghost v+ = 2 v_b - v-, same stress
+                # (Sec. 4.3 ghost states); the flux is linear in the ghost, so the wall part is
+                # taken here and the 2 v_b part below
+                Ip[vel] = ghost_state(FACE_WALL, Im[vel])
             nq = Im.shape[1]
             nn = np.broadcast_to(n[:, None, :], (n.shape[0], nq, 3))
             F = godunov_flux(Im, Ip, nn,
@@ -234,6 +260,20 @@ class Oracle:
                               rp[:, None] * np.ones(nq)))
             F[kind == FACE_GRAVITY] = 0.0
             dQ -= scale[:, None, None] * np.matmul((self.phi_f[i] * self.fw[:, None]).T, F)
+            if vel.size:
+                # 2 v_b integrated over the step, 2 (u(t1) - u(t0)), as the neighbour trace
+                # (zero own trace); the face integral with the high-order rule
+                x = self.geo.face_points(elems[vel], np.full(vel.size, i), self.hst)
+                ta = self.time + t0 * self.dt_min
+                du = (uplift(self.uplift_sources, x[..., 0], x[..., 1], ta + dt)
+                      - uplift(self.uplift_sources, x[..., 0], x[..., 1], ta))
+                nh = self.hw.size
+                Pp = np.zeros((vel.size, nh, 9))
+                Pp[..., 8] = 2.0 * du
+                omat = tuple(m[vel][:, None] * np.ones(nh) for m in matm)
+                nv = np.broadcast_to(n[vel][:, None, :], (vel.size, nh, 3))
+                Fh = godunov_flux(np.zeros_like(Pp), Pp, nv, omat, omat)
+                dQ[vel] -= scale[vel][:, None, None] * np.matmul((self.phi_h[i] * self.hw[:, None]).T, Fh)
 
         # gravity faces of this cluster (Sec. 4.3)
         gsel = np.nonzero(self.cluster[self.grav_elem] == c)[0]

@@ -13,6 +13,7 @@
 #include "assemble.hpp"
 #include "device.hpp"
 #include "energy.hpp"
+#include "forcing.hpp"
 #include "layout.hpp"
 #include "model.hpp"
 #include "probe.hpp"
@@ -78,6 +79,11 @@ struct seis_t {
   // (allocated at its first call)
   EnergyData en{};
   double* en_partial = nullptr;
+  // prescribed-velocity faces: forcing data, the source buffer and the
+  // device count of completed macro steps (the forcing's clock)
+  ForcingArgs forcing{};
+  double* uplift_src = nullptr;
+  int64_t* macro_dev = nullptr;
   // output point sets: seis_points (ids 0, 1, ...), and the sea surface and
   // the seafloor (built at their first use)
   std::vector<PointSet> psets;
@@ -194,6 +200,22 @@ int build_common(seis_t* h, DevData<double>& c) {
   }
   h->gstart[M.C] = (int64_t)gl.size();
   HIPCHK(h, upload(b, &h->glist, gl), "upload glist");
+  {
+    int64_t* ve;
+    int8_t* vf;
+    double *vdt, *vxy, *vpr;
+    HIPCHK(h, upload(b, &ve, M.v_elem), "upload velocity faces");
+    HIPCHK(h, upload(b, &vf, M.v_face), "upload velocity faces");
+    HIPCHK(h, upload(b, &vdt, M.v_dt), "upload velocity faces");
+    HIPCHK(h, upload(b, &vxy, M.v_xy), "upload velocity face points");
+    HIPCHK(h, upload(b, &vpr, M.ref.fproj), "upload face projection");
+    HIPCHK(h, b.alloc(&h->uplift_src, 1 + 5 * kMaxUpliftSources), "alloc uplift sources");
+    HIPCHK(h, hipMemset(h->uplift_src, 0, sizeof(double) * (1 + 5 * kMaxUpliftSources)), "clear uplift sources");
+    HIPCHK(h, b.alloc(&h->macro_dev, 1), "alloc macro counter");
+    HIPCHK(h, hipMemset(h->macro_dev, 0, sizeof(int64_t)), "clear macro counter");
+    h->forcing = ForcingArgs{ve, vf, vdt, vxy, vpr, M.ref.nqf, h->uplift_src, h->macro_dev, M.Bf, row_tiles(M.Bf),
+                             1 << (M.C - 1), M.dt_min, 0};
+  }
   {
     double *ad, *lmr, *gc, *tw;
     HIPCHK(h, upload(b, &ad, M.a_absdet), "upload absdet");
@@ -350,6 +372,14 @@ int do_correct(seis_t* h, int c0, int c1) {
   const Sched sc = make_sched(h);
   const int N = M.N;
   hipError_t st = timed(h, 2, ne, [&]() -> hipError_t {
+    // uplift forcing of the prescribed-velocity faces of these clusters
+    const int64_t v0 = M.vface_start[c0], nv = M.vface_start[c1 + 1] - v0;
+    if (nv > 0) {
+      const hipError_t sf = h->precision == SEIS_FP64
+                                ? launch_forcing<double>(h->forcing, h->d64.In, v0, nv, h->sub, h->stream)
+                                : launch_forcing<float>(h->forcing, h->d32.In, v0, nv, h->sub, h->stream);
+      if (sf != hipSuccess) return sf;
+    }
     if (h->kernel == SEIS_KERNEL_PLAIN) {
       if (h->precision == SEIS_FP64) return launch_correct_plain<double>(N, h->d64, e0, ne, sc, h->stream);
       return launch_correct_plain<float>(N, h->d32, e0, ne, sc, h->stream);
@@ -391,6 +421,7 @@ void maybe_advance(seis_t* h) {
   if (h->sub == (1 << (C - 1))) {
     h->sub = 0;
     h->macro_done++;
+    (void)launch_tick(h->macro_dev, h->stream);
   }
 }
 
@@ -527,7 +558,26 @@ int seis_write(seis_t* h, const double* dofs, const double* eta) {
     HIPCHK(h, hipMemcpy(h->d64.eta, eta, M.g_elem.size() * M.nq * sizeof(double), hipMemcpyHostToDevice),
            "write eta");
   }
+  // a written state starts a new run at time 0 (the clock of the uplift forcing)
+  const int64_t zero = 0;
+  HIPCHK(h, hipMemcpy(h->macro_dev, &zero, sizeof(zero), hipMemcpyHostToDevice), "reset macro counter");
+  h->macro_done = 0;
   reset_cursor(h);
+  return SEIS_OK;
+}
+
+int seis_set_uplift(seis_t* h, int n, const double* src) {
+  if (!h || n < 0 || n > kMaxUpliftSources || (n > 0 && !src)) return SEIS_EINVAL;
+  std::vector<double> buf(1 + 5 * kMaxUpliftSources, 0.0);
+  buf[0] = n;
+  for (int j = 0; j < n; ++j) {
+    if (!(src[5 * j + 3] > 0.0) || !(src[5 * j + 4] > 0.0))
+      return fail(h, SEIS_EINVAL, "uplift source width and rise time must be > 0");
+    for (int k = 0; k < 5; ++k) buf[1 + 5 * j + k] = src[5 * j + k];
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  HIPCHK(h, hipMemcpy(h->uplift_src, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice),
+         "write uplift sources");
   return SEIS_OK;
 }
 
@@ -603,6 +653,8 @@ int step_fused(seis_t* h) {
   }
   reset_cursor(h);
   h->macro_done++;
+  const hipError_t st = launch_tick(h->macro_dev, h->stream);
+  if (st != hipSuccess) return hip_fail(h, st, "macro step counter");
   return SEIS_OK;
 }
 

@@ -49,11 +49,12 @@ __global__ __launch_bounds__(64) void k_assemble(AsmInput in, AsmOutput<T> out) 
     jacobian_x(lam, mu, rho, A);
     rotation(n, Tr, Ti);
     middle_state(zpm, zsm, zpp, zsp, Gm, Gp);
-    if (kind == 4 || kind == 5) {
-      // ghost w+ = diag(m) w-: velocity flipped (wall) or stress flipped (free surface)
+    if (kind == 4 || kind == 5 || kind == 6) {
+      // ghost w+ = diag(m) w-: velocity flipped (wall; a prescribed velocity
+      // adds 2 v_b, which the inbox supplies) or stress flipped (free surface)
       for (int r = 0; r < 9; ++r)
         for (int c = 0; c < 9; ++c) {
-          const double m = (kind == 4) ? (c >= 6 ? -1.0 : 1.0) : (c < 6 ? -1.0 : 1.0);
+          const double m = (kind != 5) ? (c >= 6 ? -1.0 : 1.0) : (c < 6 ? -1.0 : 1.0);
           Gm[r * 9 + c] += Gp[r * 9 + c] * m;
         }
     }
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmInput in, AsmOutput<T> out) 
       mul9(Tr, X, Y);
       mul9(Y, Ti, X);
       for (int i = 0; i < 81; ++i) fm[i] = (T)(scale * X[i]);
-      if (paired) {
+      if (paired || kind == 6) {
         mul9(A, Gp, X);
         mul9(Tr, X, Y);
         mul9(Y, Ti, X);

@@ -167,14 +167,18 @@ __host__ __device__ inline void pointwise_coeffs(int kind, double zpm, double zs
     for (int i = 0; i < 8; ++i) { cm[i] = s * a[i]; cp[i] = s * b[i]; }
     return;
   }
-  // ghost traces: absorbing 0; wall: same traction, velocity flipped; free: traction flipped
+  // ghost traces: absorbing 0; wall: same traction, velocity flipped; free:
+  // traction flipped; prescribed velocity: as the wall, plus 2 v_b, which
+  // reaches the flux through the neighbour coefficients and the inbox
   double gs = 0.0, gv = 0.0;
-  if (kind == 4) { gs = 1.0; gv = -1.0; }
+  if (kind == 4 || kind == 6) { gs = 1.0; gv = -1.0; }
   if (kind == 5) { gs = -1.0; gv = 1.0; }
   for (int i = 0; i < 8; i += 2) {
     cm[i] = s * (a[i] + gs * b[i]);
     cm[i + 1] = s * (a[i + 1] + gv * b[i + 1]);
   }
+  if (kind == 6)
+    for (int i = 0; i < 8; ++i) cp[i] = s * b[i];
 }
 
 }  // namespace seis

@@ -66,6 +66,14 @@ struct Model {
   std::vector<int64_t> h2_start;       // [C+1]
   double g = 9.81;
 
+  // prescribed-velocity faces (uplift forcing), library element order,
+  // grouped by cluster ([vface_start[c], vface_start[c+1]))
+  std::vector<int64_t> v_elem;
+  std::vector<int8_t> v_face;
+  std::vector<double> v_dt;            // [F_v] the element's time step
+  std::vector<double> v_xy;            // [F_v][nqf][2] x, y of the face's projection rule points
+  std::vector<int64_t> vface_start;    // [C+1]
+
   // the mesh as given (caller order), kept for locating output points
   std::vector<double> xyz;             // [nv][3]
   std::vector<int64_t> tet;            // [E][4]

@@ -273,6 +273,41 @@ RefElement build_reference(int N) {
     for (int j = 0; j < Bf; ++j) VT[j * Bf + m] = V[m * Bf + j];
   lu_solve(Bf, VT, rhs, nq);  // rhs[m][q] = ell_m(point q)
   R.tw = tw;
+  {
+    // projection of a sampled face function onto P_N, evaluated at the nodes
+    const int n1 = N + 10;
+    std::vector<double> fa, fwa, fb, fwb;
+    gauss_jacobi(n1, 0.0, 0.0, fa, fwa);
+    gauss_jacobi(n1, 1.0, 0.0, fb, fwb);
+    const int nqf = n1 * n1;
+    R.nqf = nqf;
+    R.fproj_st.resize(2 * nqf);
+    std::vector<double> Psi(nqf * Bf), M(Bf * Bf, 0.0), rhs(Bf * nqf);
+    for (int j = 0; j < n1; ++j)
+      for (int i = 0; i < n1; ++i) {
+        const int q = j * n1 + i;
+        const double s = (1 + fa[i]) * (1 - fb[j]) / 4.0, t = (1 + fb[j]) / 2.0, w = fwa[i] * fwb[j] / 8.0;
+        R.fproj_st[2 * q] = s;
+        R.fproj_st[2 * q + 1] = t;
+        triangle_basis(N, s, t, psi);
+        for (int k = 0; k < Bf; ++k) {
+          Psi[q * Bf + k] = psi[k];
+          rhs[k * nqf + q] = w * psi[k];
+        }
+        for (int k = 0; k < Bf; ++k)
+          for (int l = 0; l < Bf; ++l) M[k * Bf + l] += w * psi[k] * psi[l];
+      }
+    lu_solve(Bf, M, rhs, nqf);  // rhs = M^-1 Psi^T W
+    R.fproj.assign(Bf * nqf, 0.0);
+    for (int m = 0; m < Bf; ++m)
+      for (int k = 0; k < Bf; ++k)
+        for (int q = 0; q < nqf; ++q) R.fproj[m * nqf + q] += V[m * Bf + k] * rhs[k * nqf + q];
+  }
+  R.node_st.resize(2 * Bf);
+  for (int m = 0; m < Bf; ++m) {
+    R.node_st[2 * m] = double(nodes[m][0]) / N;
+    R.node_st[2 * m + 1] = double(nodes[m][1]) / N;
+  }
 
   R.E.assign(4 * Bf * B, 0.0);
   R.L.assign(4 * B * Bf, 0.0);

@@ -32,6 +32,13 @@ struct RefElement {
   std::vector<double> Lg;  // [4][B][nq]
   std::vector<double> eta_st;  // [nq][2] face parameters of the eta points
   std::vector<double> tw;      // [nq] weights of the face rule at the eta points (sum 1/2)
+  std::vector<double> node_st; // [Bf][2] face parameters of the face nodes
+  // L2 projection onto P_N of a face of a function sampled at a high-order
+  // face rule (N + 10 Gauss points per collapsed direction), as nodal values:
+  // nodal[m] = sum_q fproj[m][q] f(point q)
+  int nqf = 0;
+  std::vector<double> fproj_st; // [nqf][2] face parameters of the rule's points
+  std::vector<double> fproj;    // [Bf][nqf]
   std::vector<int> perm;   // [6][Bf]: neighbour node index for node m under vertex map h
   std::vector<int> pinv;   // [6][Bf]: inverse of perm[h]
   std::array<std::array<int, 3>, 6> sigma{};  // the 6 vertex maps: my face vertex a -> neighbour's sigma[a]

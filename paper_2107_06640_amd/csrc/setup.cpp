@@ -48,7 +48,7 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
         return err.str();
       }
     for (int f = 0; f < 4; ++f)
-      if (face_kind[e * 4 + f] < 0 || face_kind[e * 4 + f] > 5) {
+      if (face_kind[e * 4 + f] < 0 || face_kind[e * 4 + f] > 6) {
         err << "element " << e << ": bad face kind";
         return err.str();
       }
@@ -376,6 +376,30 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
       }
     }
   }
+  // ---- prescribed-velocity faces, grouped by cluster (library order inside)
+  M.vface_start.assign(C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    M.vface_start[c] = (int64_t)M.v_elem.size();
+    for (int64_t kn = M.cluster_start[c]; kn < M.cluster_start[c + 1]; ++kn) {
+      const int64_t e = M.old_of_new[kn];
+      for (int f = 0; f < 4; ++f) {
+        if (face_kind[e * 4 + f] != 6) continue;
+        M.v_elem.push_back(kn);
+        M.v_face.push_back(int8_t(f));
+        M.v_dt.push_back(M.dt_c[c]);
+        const double* X[4];
+        for (int v = 0; v < 4; ++v) X[v] = xyz + 3 * tet[e * 4 + v];
+        for (int m = 0; m < R.nqf; ++m) {
+          double xi[3];
+          face_to_ref(f, R.fproj_st[2 * m], R.fproj_st[2 * m + 1], xi);
+          for (int d = 0; d < 2; ++d)
+            M.v_xy.push_back(X[0][d] + (X[1][d] - X[0][d]) * xi[0] + (X[2][d] - X[0][d]) * xi[1] +
+                             (X[3][d] - X[0][d]) * xi[2]);
+        }
+      }
+    }
+  }
+  M.vface_start[C] = (int64_t)M.v_elem.size();
   M.xyz.assign(xyz, xyz + nv * 3);
   M.tet.assign(tet, tet + E * 4);
   M.g_order.resize(M.g_elem.size());

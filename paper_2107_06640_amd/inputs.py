@@ -13,7 +13,8 @@ so these boxes stand in for them.
 
 Face-kind codes (face i of a tetrahedron is the face opposite its local vertex i):
     0 interior, 1 periodic, 2 gravity free surface, 3 absorbing (zero ghost),
-    4 rigid wall, 5 traction-free surface (g = 0).
+    4 rigid wall, 5 traction-free surface (g = 0), 6 prescribed velocity
+    (the uplift history of the seafloor forcing).
 """
 from __future__ import annotations
 
@@ -28,6 +29,7 @@ FACE_GRAVITY = 2
 FACE_ABSORBING = 3
 FACE_WALL = 4
 FACE_FREE = 5
+FACE_VELOCITY = 6
 
 _KIND = {
     "periodic": FACE_PERIODIC,
@@ -35,6 +37,7 @@ _KIND = {
     "absorbing": FACE_ABSORBING,
     "wall": FACE_WALL,
     "free": FACE_FREE,
+    "velocity": FACE_VELOCITY,
 }
 
 # Rock and water parameters of the paper's coupled setting (Sec. 3); the rock

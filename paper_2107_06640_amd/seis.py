@@ -23,7 +23,7 @@ ERRORS = {-1: "SEIS_EINVAL", -2: "SEIS_ENOMEM", -3: "SEIS_EDEVICE", -4: "SEIS_EO
 EXPORTED = ["seis_default_options", "seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step",
             "seis_run", "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
             "seis_destroy", "seis_last_error", "seis_profile", "seis_profile_read", "seis_energy",
-            "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample"]
+            "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample", "seis_set_uplift"]
 SEIS_POINTS_SEA_SURFACE, SEIS_POINTS_SEAFLOOR = -1, -2
 
 
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.seis_points.argtypes = [P, C.c_int64, dp, C.POINTER(C.c_int)]
     lib.seis_points_info.argtypes = [P, C.c_int, C.POINTER(C.c_int64), dp, C.POINTER(C.c_int64)]
     lib.seis_sample.argtypes = [P, C.c_int, C.c_void_p, C.c_void_p]
+    lib.seis_set_uplift.argtypes = [P, C.c_int, dp]
     lib.seis_energy_noalloc.argtypes = [P, C.c_void_p]
     lib.seis_destroy.argtypes = [P]
     lib.seis_destroy.restype = None
@@ -107,7 +108,7 @@ def load_library(path: str = LIB_PATH):
     lib.seis_last_error.restype = C.c_char_p
     for name in ("seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step", "seis_run",
                  "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
-                 "seis_profile", "seis_profile_read", "seis_energy", "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample"):
+                 "seis_profile", "seis_profile_read", "seis_energy", "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample", "seis_set_uplift"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -185,6 +186,11 @@ class Solver:
             raise ValueError(f"eta must have shape {(self.n_gravity_faces, self.nq)}")
         self._check(self._lib.seis_write(self._h, None if d is None else _ptr(d, C.c_double),
                                          None if e is None else _ptr(e, C.c_double)))
+
+    def set_uplift(self, sources):
+        """Uplift history of the prescribed-velocity faces: sources [n][5] = (A, x, y, w, T)."""
+        src = np.ascontiguousarray(sources, dtype=np.float64).reshape(-1, 5)
+        self._check(self._lib.seis_set_uplift(self._h, src.shape[0], _ptr(src, C.c_double)))
 
     def predict(self, c):
         self._check(self._lib.seis_predict(self._h, int(c)))
