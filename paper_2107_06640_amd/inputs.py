@@ -337,10 +337,14 @@ def cfg2(scale: int = 1, seed: int = 0):
     return m, mat
 
 
-def cfg5(scale: int = 1, seed: int = 0):
-    """24x24x12 cubes of 1 km x 6 tets (41 472 elements), top 3 layers water (surrogate data)."""
+def cfg5(scale: int = 1, seed: int = 0, bottom: str = "absorbing"):
+    """24x24x12 cubes of 1 km x 6 tets (41 472 elements), top 3 layers water (surrogate data).
+
+    bottom="velocity" makes the bottom of the solid the prescribed-velocity
+    boundary that the uplift history drives.
+    """
     nx, ny, nz = 24 // scale, 24 // scale, 12 // scale
-    m, mat = coupled_box(nx, ny, nz, cell=1000.0, water_layers=max(1, nz // 4), seed=seed)
+    m, mat = coupled_box(nx, ny, nz, cell=1000.0, water_layers=max(1, nz // 4), seed=seed, bottom=bottom)
     m.info.update(name="cfg5-surrogate")
     return m, mat
 
