@@ -45,30 +45,40 @@ def nf(N):
     return (N + 1) * (N + 2) // 2
 
 
-def algorithmic_counts(N, value_bytes):
+def algorithmic_counts(N, value_bytes, acoustic=False):
     """Per-element algorithmic flops and HBM bytes of the predictor and corrector kernels.
 
-    Flops: CK with shrinking support (star matrices at 24 non-zeros), the time
-    integral, the volume term over the B_{N-1} non-zero columns of K^d, face
-    traces and lifts at B_f nodes (2 B_f B 9 each per face) and the pointwise
-    Riemann solve (9 x 9 per node). Bytes: what the executed form must move
-    at least once: the predictor reads Q, G (9), material (3) and the own-trace
-    flux coefficients (4 x 12) and writes Q and the 4 B_f x 9 traces it hands
-    over; the corrector reads its 4 B_f x 9 inbox, material, the neighbour-
-    trace coefficients (4 x 12) and reads and writes Q.
+    Nine-quantity form. Flops: CK with shrinking support (star matrices at 24
+    non-zeros), the time integral, the volume term over the B_{N-1} non-zero
+    columns of K^d, face traces and lifts at B_f nodes (2 B_f B 9 each per
+    face) and the pointwise Riemann solve (9 x 9 per node). Bytes: what the
+    executed form must move at least once: the predictor reads Q, G (9),
+    material (3) and the own-trace flux coefficients (4 x 12) and writes Q and
+    the 4 B_f x 9 traces it hands over; the corrector reads its 4 B_f x 9
+    inbox, material, the neighbour-trace coefficients (4 x 12) and reads and
+    writes Q.
+
+    4-quantity form (acoustic=True, s_xx = -p and the velocity): 4 columns in
+    every contraction, star matrices at 18 non-zeros (per direction three in
+    the pressure row, one in each velocity row), the own-trace Riemann solve
+    4 x 4 and the neighbour-trace one 4 x 9 per node; Q and the traces at 4
+    values per row.
     """
     B, Bf, B1 = nb(N), nf(N), nb(N - 1)
-    ck = sum(2 * 3 * nb(N - k - 1) * nb(N - k) * 9 + 2 * nb(N - k - 1) * 72 for k in range(N))
-    tint = sum(2 * nb(N - k) * 9 for k in range(N + 1))
-    traces = 2 * 4 * Bf * B * 9
-    flux = 2 * 4 * Bf * 81
-    volume = 2 * B1 * 72 + 2 * B * 3 * B1 * 9
-    lift = 2 * 4 * B * Bf * 9
-    pred_flops = ck + tint + traces + flux + volume + lift
-    corr_flops = flux + lift
+    q = 4 if acoustic else 9
+    nz = 18 if acoustic else 72
+    ck = sum(2 * 3 * nb(N - k - 1) * nb(N - k) * q + 2 * nb(N - k - 1) * nz for k in range(N))
+    tint = sum(2 * nb(N - k) * q for k in range(N + 1))
+    traces = 2 * 4 * Bf * B * q
+    flux_own = 2 * 4 * Bf * q * q
+    flux_nb = 2 * 4 * Bf * q * 9
+    volume = 2 * B1 * nz + 2 * B * 3 * B1 * q
+    lift = 2 * 4 * B * Bf * q
+    pred_flops = ck + tint + traces + flux_own + volume + lift
+    corr_flops = flux_nb + lift
     vb = value_bytes
-    pred_bytes = vb * (B * 9 + 12 + 4 * 12 + 4 * Bf * 9 + B * 9)
-    corr_bytes = vb * (4 * Bf * 9 + 3 + 4 * 12 + 2 * B * 9)
+    pred_bytes = vb * (B * q + 12 + 4 * 12 + 4 * Bf * q + B * q)
+    corr_bytes = vb * (4 * Bf * q + 3 + 4 * 12 + 2 * B * q)
     return dict(pred_flops=pred_flops, corr_flops=corr_flops, pred_bytes=pred_bytes, corr_bytes=corr_bytes)
 
 
@@ -254,7 +264,11 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="replay each macro step as one hipGraph; kernel timings then come from a "
                          "separate eagerly launched pass of the same length")
+    ap.add_argument("--nine-quantity-water", action="store_true",
+                    help="acoustic elements in the nine-quantity embedding everywhere (no 4-quantity groups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="FP32 runs: skip the BF16-operand measurement reported beside the FP32 line")
     ap.add_argument("--sweep", action="store_true",
                     help="precision sweep: FP32/BF16 against FP64 at orders 4-7 (one JSON line each)")
     ap.add_argument("--sweep-orders", type=int, nargs="+", default=[4, 5, 6, 7])
@@ -285,76 +299,14 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2107_06640_amd import seis
 
-    t_setup = time.perf_counter()
     mesh, mats = workload(args.scale, name=args.workload)
-    rho, lam, mu = mats
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    s = seis.from_mesh(mesh, mats, args.order, precision=args.precision, kernel=args.kernel,
-                       max_clusters=args.max_clusters, stream=stream.cuda_stream, tile=args.tile,
-                       graph=args.graph, mc_min=args.mc_min, fused=not args.per_cluster)
-    inf = s.info()
-    q = tiled_dofs(mesh.n_elements, inf["n_basis"], 0, mu == 0)
-    s.write(q)
-    del q
-    t_setup = time.perf_counter() - t_setup
-    print(f"# setup {t_setup:.1f} s, E={inf['n_elements']}, clusters={inf['cluster_size']}, "
-          f"updates/macro={inf['updates_per_macro_step']}", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        s.step()
-    s.sync()
-    torch.cuda.synchronize()
-
-    def timed_steps(profile):
-        s.profile(profile)
-        start = torch.cuda.Event(enable_timing=True)
-        stop = torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        for _ in range(args.steps):
-            s.step()
-        stop.record(stream)
-        stop.synchronize()
-        torch.cuda.synchronize()
-        prof = s.profile_read() if profile else None
-        s.profile(False)
-        return start.elapsed_time(stop), prof
-
-    if args.graph:
-        ms, _ = timed_steps(False)       # graph replays
-        eager_ms, prof = timed_steps(True)
-    else:
-        ms, prof = timed_steps(True)
-        eager_ms = ms
-    upd = inf["updates_per_macro_step"] * args.steps
-    value = upd / (ms / 1e3)
-
-    N = args.order - 1
-    cnt = algorithmic_counts(N, BYTES[args.precision])
-    pms, pl, pe = prof["predict"]
-    cms, cl, ce = prof["correct"]
-    dom = "predict" if pms >= cms else "correct"
-    kms, kl, ke = prof[dom]
-    flops = cnt["pred_flops" if dom == "predict" else "corr_flops"] * ke / kl
-    byts = cnt["pred_bytes" if dom == "predict" else "corr_bytes"] * ke / kl
-    avg_s = kms / kl / 1e3
-    peak_tf = PEAK[{"fp64": "fp64_TF", "fp32": "fp32_TF", "bf16": "bf16_TF"}[args.precision]]
-    t_flop = flops / (peak_tf * 1e12)
-    t_byte = byts / (PEAK["hbm_GBs"] * 1e9)
-    if t_flop >= t_byte:
-        bound = "mfma" if args.kernel == "tuned" else "alu"
-        roof = dict(bound=bound, achieved=flops / avg_s / 1e12, peak=peak_tf, unit="TFLOP/s")
-    else:
-        roof = dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom, args.precision, args.kernel, args.order) \
-        if args.workload == "cfg3" else None
-    roof["traffic_source"] = ("stored rocprofv3 FETCH_SIZE/WRITE_SIZE of these kernel sources "
-                              "(profiles/traffic_cfg3_order6.json)") if roof["traffic"] is not None else None
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = kms / kl
+    run = measure(args, mesh, mats, args.precision, stream)
+    inf, ms, eager_ms, prof = run["info"], run["ms"], run["eager_ms"], run["prof"]
+    value = inf["updates_per_macro_step"] * args.steps / (ms / 1e3)
+    roof = roofline(args, args.precision, inf, prof)
 
     out = {
         "metric": "ADER-DG element-updates/s (order 6), FP32/BF16 vs FP64, % of roofline",
@@ -367,7 +319,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}[args.precision],
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: graded jittered ocean-over-solid box "
                                f"(jitter {WORKLOADS[args.workload]}), {inf['n_elements']} tets, "
@@ -377,20 +329,138 @@ def main():
                    "graph": bool(args.graph), "fused": bool(inf["fused"]),
                    "eager_ms_per_step": eager_ms / args.steps,
                    "launches_per_step": {k: v[1] / args.steps for k, v in prof.items()},
-                   "launch": {"predict": inf["launch"][:3], "correct": inf["launch"][3:7],
-                              "mc_min": inf["launch"][7],
-                              "predict_shape": {("fp32", 0): "I~ park LDS", ("fp32", 1): "I~ park HBM",
-                                                ("bf16", 0): "bf16 16x16x16", ("bf16", 1): "bf16 16x16x32"}.get(
-                                                    (args.precision, inf["shape"]), "plain"),
-                              "source": ["default", "measured", "cache"][inf["launch_source"]]},
+                   "launch": launch_record(args.precision, inf),
+                   "acoustic_groups": inf["n_acoustic_groups"],
+                   "acoustic_fraction": acoustic_fraction(inf),
                    "updates_per_step": inf["updates_per_macro_step"]},
         "roofline": roof,
         "kernels_ms": {k: v[0] for k, v in prof.items()},
     }
-    s.close()
+    if args.precision == "fp32" and args.kernel == "tuned" and not args.no_bf16:
+        # the BF16-operand kernels on the same workload, same steps and timing
+        b = measure(args, mesh, mats, "bf16", stream)
+        bi = b["info"]
+        out["bf16"] = {
+            "value": bi["updates_per_macro_step"] * args.steps / (b["ms"] / 1e3),
+            "ms_per_step": b["ms"] / args.steps,
+            "dtype": DTYPE["bf16"],
+            "launch": launch_record("bf16", bi),
+            "roofline": roofline(args, "bf16", bi, b["prof"]),
+            "kernels_ms": {k: v[0] for k, v in b["prof"].items()},
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.order)
     print(json.dumps(out), flush=True)
+
+
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}
+
+
+def measure(args, mesh, mats, precision, stream):
+    """Set up the solver, warm up, and time args.steps macro steps on the library's stream.
+
+    Returns the solver info, the event-timed milliseconds of the timed steps
+    (graph replays with --graph), those of an eagerly launched pass, and the
+    per-kernel profile (milliseconds, launches, elements) of the eager pass.
+    """
+    import torch
+    from paper_2107_06640_amd import seis
+
+    t_setup = time.perf_counter()
+    s = seis.from_mesh(mesh, mats, args.order, precision=precision, kernel=args.kernel,
+                       max_clusters=args.max_clusters, stream=stream.cuda_stream, tile=args.tile,
+                       graph=args.graph, mc_min=args.mc_min, fused=not args.per_cluster,
+                       acoustic=not args.nine_quantity_water)
+    try:
+        inf = s.info()
+        q = tiled_dofs(mesh.n_elements, inf["n_basis"], 0, mats[2] == 0)
+        s.write(q)
+        del q
+        t_setup = time.perf_counter() - t_setup
+        print(f"# {precision}: setup {t_setup:.1f} s, E={inf['n_elements']}, clusters={inf['cluster_size']}, "
+              f"updates/macro={inf['updates_per_macro_step']}, 4-quantity groups={inf['n_acoustic_groups']}",
+              file=sys.stderr, flush=True)
+
+        for _ in range(args.warmup):
+            s.step()
+        s.sync()
+        torch.cuda.synchronize()
+
+        def timed_steps(profile):
+            s.profile(profile)
+            start = torch.cuda.Event(enable_timing=True)
+            stop = torch.cuda.Event(enable_timing=True)
+            start.record(stream)
+            for _ in range(args.steps):
+                s.step()
+            stop.record(stream)
+            stop.synchronize()
+            torch.cuda.synchronize()
+            prof = s.profile_read() if profile else None
+            s.profile(False)
+            return start.elapsed_time(stop), prof
+
+        if args.graph:
+            ms, _ = timed_steps(False)       # graph replays
+            eager_ms, prof = timed_steps(True)
+        else:
+            ms, prof = timed_steps(True)
+            eager_ms = ms
+        return dict(info=inf, ms=ms, eager_ms=eager_ms, prof=prof)
+    finally:
+        s.close()
+
+
+def acoustic_fraction(inf):
+    """Share of the elements that sit in 16-element groups of the 4-quantity form."""
+    return min(1.0, 16.0 * inf["n_acoustic_groups"] / inf["n_elements"])
+
+
+def launch_record(precision, inf):
+    return {"predict": inf["launch"][:3], "correct": inf["launch"][3:7], "mc_min": inf["launch"][7],
+            "predict_shape": {("fp32", 0): "I~ park LDS", ("fp32", 1): "I~ park HBM",
+                              ("bf16", 0): "bf16 16x16x16", ("bf16", 1): "bf16 16x16x32"}.get(
+                                  (precision, inf["shape"]), "plain"),
+            "source": ["default", "measured", "cache"][inf["launch_source"]]}
+
+
+def roofline(args, precision, inf, prof):
+    """Roofline object of the dominant kernel from its event-timed launches.
+
+    The algorithmic work per element is that of the form the element runs
+    in: the acoustic_fraction of the elements count with the 4-quantity
+    figures, the rest with the nine-quantity ones.
+    """
+    N = args.order - 1
+    c9 = algorithmic_counts(N, BYTES[precision])
+    c4 = algorithmic_counts(N, BYTES[precision], acoustic=True)
+    fa = acoustic_fraction(inf) if args.kernel == "tuned" and precision != "fp64" else 0.0
+    cnt = {k: (1.0 - fa) * c9[k] + fa * c4[k] for k in c9}
+    pms, pl, pe = prof["predict"]
+    cms, cl, ce = prof["correct"]
+    dom = "predict" if pms >= cms else "correct"
+    kms, kl, ke = prof[dom]
+    flops = cnt["pred_flops" if dom == "predict" else "corr_flops"] * ke / kl
+    byts = cnt["pred_bytes" if dom == "predict" else "corr_bytes"] * ke / kl
+    avg_s = kms / kl / 1e3
+    peak_tf = PEAK[{"fp64": "fp64_TF", "fp32": "fp32_TF", "bf16": "bf16_TF"}[precision]]
+    t_flop = flops / (peak_tf * 1e12)
+    t_byte = byts / (PEAK["hbm_GBs"] * 1e9)
+    if t_flop >= t_byte:
+        bound = "mfma" if args.kernel == "tuned" else "alu"
+        roof = dict(bound=bound, achieved=flops / avg_s / 1e12, peak=peak_tf, unit="TFLOP/s")
+    else:
+        roof = dict(bound="hbm", achieved=byts / avg_s / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(dom, precision, args.kernel, args.order) \
+        if args.workload == "cfg3" else None
+    roof["traffic_source"] = ("stored rocprofv3 FETCH_SIZE/WRITE_SIZE of these kernel sources "
+                              "(profiles/traffic_cfg3_order6.json)") if roof["traffic"] is not None else None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = kms / kl
+    roof["flops_per_launch"] = flops
+    roof["bytes_per_launch"] = byts
+    return roof
 
 
 if __name__ == "__main__":

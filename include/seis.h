@@ -117,6 +117,15 @@ typedef struct {
                        elements, else on the plain FP32 kernels; 0: one launch per cluster, each
                        cluster's kernel chosen by its own size. seis_predict/seis_correct always work
                        per cluster. */
+  int acoustic;     /* tuned kernels, FP32/BF16: nonzero (default) runs each 16-element group whose
+                       elements are all acoustic (mu = 0) in the 4-quantity form (Sec. 4.1: the stress
+                       is -p I there): s_xx = -p and the velocity are integrated, s_yy and s_zz are
+                       stored equal to s_xx and the shear components as zero, and the face fluxes of
+                       such an element read the neighbour's full nine-quantity trace (elastic at the
+                       seafloor). The state of an acoustic element is then taken to be isotropic:
+                       s_yy, s_zz and the shear components written by seis_write are not read there.
+                       Set-up orders the acoustic elements of a cluster together. 0: the
+                       nine-quantity embedding everywhere. */
 } seis_options_t;
 
 typedef struct {
@@ -143,10 +152,12 @@ typedef struct {
   int fused;            /* options.fused */
   int shape;            /* the predictor's shape: FP32 0 = I~ parked in LDS as far as it fits,
                            1 = in HBM; BF16 0 = 16x16x16 products, 1 = 16x16x32 products */
+  int64_t n_acoustic_groups; /* 16-element groups run in the 4-quantity form (options.acoustic) */
 } seis_info_t;
 
 /* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream,
- * eager launches (no graph), mc_min 2048, fused sub-step launches. */
+ * eager launches (no graph), mc_min 2048, fused sub-step launches, 4-quantity
+ * acoustic groups. */
 void seis_default_options(seis_options_t *opt);
 
 /* Build the solver for a mesh (Sec. 4.1-4.4): validate, match faces,

@@ -444,6 +444,7 @@ void seis_default_options(seis_options_t* o) {
   o->graph = 0;
   o->mc_min = 2048;
   o->fused = 1;
+  o->acoustic = 1;
 }
 
 int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, const seis_options_t* opt,
@@ -510,7 +511,8 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
     }
   }
   if (rc == SEIS_OK && o.kernel == SEIS_KERNEL_TUNED) {
-    hipError_t st = tuned_build(h->tuned, h->M, h->precision, h->d64, h->d32, h->tile, h->buf.ptrs, h->buf.bytes);
+    hipError_t st = tuned_build(h->tuned, h->M, h->precision, h->d64, h->d32, h->tile, o.acoustic != 0, h->buf.ptrs,
+                                h->buf.bytes);
     if (st != hipSuccess) rc = hip_fail(h, st, "tuned set-up");
   }
   if (rc == SEIS_OK) rc = assemble_ops(h);
@@ -823,6 +825,7 @@ int seis_info(const seis_t* h, seis_info_t* info) {
   info->launch_source = h->tuned.source;
   info->fused = h->fused ? 1 : 0;
   info->shape = h->tuned.pc.variant;
+  info->n_acoustic_groups = h->tuned.n_acoustic_groups;
   return SEIS_OK;
 }
 

@@ -277,8 +277,10 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
   M.cluster_old = cl;
 
   // ---- element order: by cluster; inside a cluster, elements with a
-  // neighbour in another cluster last (stable), so that the hand-over branches
-  // of the matrix-core kernels diverge in few element groups
+  // neighbour in another cluster last, so that the hand-over branches of the
+  // matrix-core kernels diverge in few element groups, and inside each of
+  // those the acoustic elements first, so that whole 16-element groups are
+  // acoustic (the 4-quantity form); stable otherwise
   std::vector<int8_t> iface(E, 0);
   for (int64_t id = 0; id < E * 4; ++id)
     if (nb[id] >= 0 && cl[nb[id] / 4] != cl[id / 4]) iface[id / 4] = 1;
@@ -286,7 +288,8 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
   std::iota(M.old_of_new.begin(), M.old_of_new.end(), 0);
   std::stable_sort(M.old_of_new.begin(), M.old_of_new.end(), [&](int64_t a, int64_t b) {
     if (cl[a] != cl[b]) return cl[a] < cl[b];
-    return iface[a] < iface[b];
+    if (iface[a] != iface[b]) return iface[a] < iface[b];
+    return (mu[a] > 0.0) < (mu[b] > 0.0);
   });
   M.new_of_old.resize(E);
   for (int64_t k = 0; k < E; ++k) M.new_of_old[M.old_of_new[k]] = k;

@@ -159,7 +159,8 @@ std::vector<double> ref_image_n(const Model& M, int& bytes) {
 }  // namespace
 
 hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevData<double>& d64,
-                       const DevData<float>& d32, int tile, std::vector<void*>& owned, int64_t& bytes) {
+                       const DevData<float>& d32, int tile, int acoustic, std::vector<void*>& owned,
+                       int64_t& bytes) {
   t.N = M.N;
   t.precision = precision;
   t.d64 = d64;
@@ -234,6 +235,23 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
     a.dslot = ds;
     a.fix_list = fl;
     a.h2_list = hl;
+  }
+  {
+    // 16-element groups of acoustic elements (mu = 0) run in the 4-quantity
+    // form; element order puts the acoustic elements of a cluster together
+    const int64_t ng = (M.E + 15) / 16;
+    std::vector<int32_t> gac(ng, 0);
+    t.n_acoustic_groups = 0;
+    for (int64_t gi = 0; gi < ng && acoustic; ++gi) {
+      bool all = true;
+      for (int64_t e = gi * 16; e < std::min<int64_t>(M.E, gi * 16 + 16); ++e) all = all && M.a_lmr[e * 3 + 1] == 0.0;
+      gac[gi] = all ? 1 : 0;
+      t.n_acoustic_groups += gac[gi];
+    }
+    int32_t* dg;
+    st = upload(owned, bytes, &dg, gac);
+    if (st != hipSuccess) return st;
+    a.gac = dg;
   }
   // LDS image of the reference matrices (layout of Lay<Op, N>), padded to 16 bytes
   int lbytes = 0;

@@ -32,6 +32,8 @@ struct TArgs {
   const int32_t* fix_list;  // element * 4 + face of the faces handing over to a finer neighbour
   const int32_t* h2_list;   // element * 4 + face of the faces reading a second-half slot
   float* Ib;            // tiled [E][B][9]: time-integrated predictor I~ = Q + J, parked by the predictor
+  const int32_t* gac;   // [ceil(E/16)]: 1 where every element of the 16-element group is acoustic
+                        // (run in the 4-quantity form), else 0
   const void* ref;      // reference matrices K | E | L in operand precision
   int ref_bytes;
 };
@@ -54,6 +56,7 @@ struct TunedData {
   int fixed = 0;         // configuration fixed by the caller (options.tile)
   int source = 0;        // 0 default or fixed, 1 measured at set-up, 2 read from the tuning cache
   int64_t mc_min = 0;    // clusters with fewer elements run on the plain FP32 kernels
+  int64_t n_acoustic_groups = 0;  // 16-element groups run in the 4-quantity form
   TArgs a{};
   std::vector<int64_t> fix_start, h2_start;  // per cluster: ranges of fix_list and h2_list
   DevData<double> d64{};
@@ -68,8 +71,11 @@ hipError_t pred_dispatch_bf16(int N, const LaunchCfg& c, const TArgs& a, int64_t
 hipError_t corr_dispatch_f32(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s);
 hipError_t corr_dispatch_bf16(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s);
 
+// acoustic: nonzero runs 16-element groups of acoustic elements in the
+// 4-quantity form.
 hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevData<double>& d64,
-                       const DevData<float>& d32, int tile, std::vector<void*>& owned, int64_t& bytes);
+                       const DevData<float>& d32, int tile, int acoustic, std::vector<void*>& owned,
+                       int64_t& bytes);
 // Clusters c0..c1 = elements [e0, e1) (a launch may span several clusters;
 // sc gives each element's step parity). FP64 runs the plain kernels, and so
 // does a range of fewer than mc_min elements (in FP32). Otherwise the

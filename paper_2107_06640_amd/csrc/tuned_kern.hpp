@@ -122,6 +122,45 @@ __device__ __forceinline__ void flux_comp(const float* u, float lam, float mu, f
   if constexpr (p == 8) { ux = -rinv * u[5]; uy = -rinv * u[4]; uz = -rinv * u[2]; }
 }
 
+// Quantities carried by a 16-element group in the 4-quantity form (AC), used
+// when every element of the group is acoustic: with mu = 0 the stress is -p I
+// (Sec. 4.1), so s_yy and s_zz equal s_xx and the shear components vanish;
+// s_xx (= -p) and the velocity remain. The 9-quantity form carries all nine.
+template <bool AC>
+__host__ __device__ constexpr bool carried(int p) {
+  return !AC || p == 0 || p >= 6;
+}
+
+// complete a state of the 4-quantity form to the nine quantities of the embedding
+template <bool AC>
+__device__ __forceinline__ void embed(float (&u)[9]) {
+  if constexpr (AC) {
+    u[1] = u[0];
+    u[2] = u[0];
+    u[3] = 0.0f;
+    u[4] = 0.0f;
+    u[5] = 0.0f;
+  }
+}
+
+// apply_star for either form: with mu = 0 the three normal-stress rows
+// coincide and the shear rows vanish, and the velocity rows see only s_xx.
+// The terms kept are those of the 9-quantity form that are not products
+// with a zero.
+template <bool AC>
+__device__ __forceinline__ void star_q(float cx, float cy, float cz, float lam, float mu, float rinv,
+                                       const float (&v)[9], float (&out)[9]) {
+  if constexpr (!AC) {
+    apply_star(cx, cy, cz, lam, mu, rinv, v, out);
+  } else {
+    const float nlam = -lam, nr = -rinv;
+    out[0] = nlam * cx * v[6] + nlam * cy * v[7] + nlam * cz * v[8];
+    out[6] = nr * (cx * v[0]);
+    out[7] = nr * (cy * v[0]);
+    out[8] = nr * (cz * v[0]);
+  }
+}
+
 // Minus the Godunov flux A-hat^-(n) q^b at one face node (Sec. 4.2), with the
 // middle state a linear map of the given trace: c = n_x, n_y, n_z, then the
 // eight scaled coefficients of (s_n^b, v_n^b) from (s_n, v_n) and
@@ -151,6 +190,43 @@ __device__ __forceinline__ void node_flux(const float* c, float lam, float mu, f
   out[6] = rinv * (snb * nx + tbx);
   out[7] = rinv * (snb * ny + tby);
   out[8] = rinv * (snb * nz + tbz);
+}
+
+// node_flux for the rows an element of the 4-quantity form carries (AC: s_xx,
+// where mu = 0 leaves lam v_n^b, and the velocity), from a trace of that form
+// (IN_AC: traction s_xx n) or a full trace (the neighbour's trace: elastic at
+// the seafloor). The terms kept are those of node_flux that are not products
+// with a zero.
+template <bool AC, bool IN_AC>
+__device__ __forceinline__ void node_flux_q(const float* c, float lam, float mu, float rinv, const float (&in)[9],
+                                            float (&out)[9]) {
+  static_assert(AC || !IN_AC, "a trace of the 4-quantity form belongs to an element of that form");
+  if constexpr (!AC) {
+    node_flux(c, lam, mu, rinv, in, out);
+  } else {
+    const float nx = c[0], ny = c[1], nz = c[2];
+    float tx, ty, tz;
+    if constexpr (IN_AC) {
+      tx = in[0] * nx;
+      ty = in[0] * ny;
+      tz = in[0] * nz;
+    } else {
+      tx = in[0] * nx + in[3] * ny + in[5] * nz;
+      ty = in[3] * nx + in[1] * ny + in[4] * nz;
+      tz = in[5] * nx + in[4] * ny + in[2] * nz;
+    }
+    const float sn = tx * nx + ty * ny + tz * nz;
+    const float ttx = tx - sn * nx, tty = ty - sn * ny, ttz = tz - sn * nz;
+    const float vn = in[6] * nx + in[7] * ny + in[8] * nz;
+    const float vtx = in[6] - vn * nx, vty = in[7] - vn * ny, vtz = in[8] - vn * nz;
+    const float snb = c[3] * sn + c[4] * vn;
+    const float vnb = c[5] * sn + c[6] * vn;
+    const float tbx = c[7] * ttx + c[8] * vtx, tby = c[7] * tty + c[8] * vty, tbz = c[7] * ttz + c[8] * vtz;
+    out[0] = lam * vnb;
+    out[6] = rinv * (snb * nx + tbx);
+    out[7] = rinv * (snb * ny + tby);
+    out[8] = rinv * (snb * nz + tbz);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -268,7 +344,9 @@ constexpr int kPrefetch = 2;
 // runs over state rows (row 16t + 4v + g in register v of lane group g) and
 // the output rows are face nodes. Either way a slab (t, v) holds K entries
 // 16t + 4v .. 16t + 4v + 3, so a partial last tile needs only its first slabs.
-template <class Op, class V, int NT, int MT, bool PIPE = false, bool NODEK = false, class RowFn>
+// AC: only the quantities of the 4-quantity form (the others of acc and of
+// the rows are neither read nor written).
+template <class Op, class V, int NT, int MT, bool PIPE = false, bool NODEK = false, bool AC = false, class RowFn>
 __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nrows, int el, int g, RowFn rowfn) {
   if constexpr (!is_bf<Op>) {
     constexpr int D = PIPE ? kPrefetch : 0;  // rows requested ahead
@@ -305,7 +383,8 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
       for (int mt = 0; mt < MT; ++mt) {
         const float a = an[i & 1][mt];
 #pragma unroll
-        for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, cur[p], acc[mt][p], 0, 0, 0);
+        for (int p = 0; p < 9; ++p)
+          if (carried<AC>(p)) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, cur[p], acc[mt][p], 0, 0, 0);
       }
       if constexpr (PIPE) __builtin_amdgcn_sched_barrier(0);
     }
@@ -331,6 +410,7 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
       }
 #pragma unroll
       for (int p = 0; p < 9; ++p) {
+        if (!carried<AC>(p)) continue;
         const s4 b0 = pack4(c0[0][p], c0[1][p], c0[2][p], c0[3][p]);
         const s4 b1 = two ? pack4(c1[0][p], c1[1][p], c1[2][p], c1[3][p]) : s4{0, 0, 0, 0};
 #pragma unroll
@@ -369,12 +449,14 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
       }
       s4 b[9];
 #pragma unroll
-      for (int p = 0; p < 9; ++p) b[p] = pack4(cur[0][p], cur[1][p], cur[2][p], cur[3][p]);
+      for (int p = 0; p < 9; ++p)
+        if (carried<AC>(p)) b[p] = pack4(cur[0][p], cur[1][p], cur[2][p], cur[3][p]);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const s4 a = an[t & 1][mt];
 #pragma unroll
-        for (int p = 0; p < 9; ++p) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], acc[mt][p], 0, 0, 0);
+        for (int p = 0; p < 9; ++p)
+          if (carried<AC>(p)) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], acc[mt][p], 0, 0, 0);
       }
       if constexpr (PIPE) __builtin_amdgcn_sched_barrier(0);
     }
@@ -382,18 +464,20 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
 }
 
 // accumulate J += w D
-template <int RT, int RTO>
+template <bool AC, int RT, int RTO>
 __device__ __forceinline__ void accum(float (&I)[RT][4][9], const float (&d)[RTO][4][9], float w) {
 #pragma unroll
   for (int t = 0; t < RTO; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int p = 0; p < 9; ++p) I[t][v][p] += w * d[t][v][p];
+      for (int p = 0; p < 9; ++p)
+        if (carried<AC>(p)) I[t][v][p] += w * d[t][v][p];
 }
 
-// store a derivative (rows held in x, zero beyond) for the gravity kernel
-template <int N, int RTX>
+// store a derivative (rows held in x, zero beyond) for the gravity kernel,
+// completed to nine quantities
+template <int N, bool AC, int RTX>
 __device__ __forceinline__ void store_deriv(float* dst, const float (&x)[RTX][4][9], int g) {
   constexpr int B = nbasis(N), RT = row_tiles(B);
 #pragma unroll
@@ -403,14 +487,18 @@ __device__ __forceinline__ void store_deriv(float* dst, const float (&x)[RTX][4]
       const int row = 16 * t + 4 * v + g;
       if (row >= B) continue;
 #pragma unroll
-      for (int p = 0; p < 9; ++p) dst[row * 9 + p] = (t < RTX) ? x[t < RTX ? t : 0][v][p] : 0.0f;
+      for (int p = 0; p < 9; ++p) {
+        const int pc = carried<AC>(p) ? p : (p < 3 ? 0 : -1);  // quantity the value comes from
+        dst[row * 9 + p] = (t < RTX && pc >= 0) ? x[t < RTX ? t : 0][v][pc < 0 ? 0 : pc] : 0.0f;
+      }
     }
 }
 
 // One Cauchy-Kowalevski step D(K+1) = fk sum_d (K^d)^T (D(K) (dt A*_d)^T) for the
-// output quantities [P0, P1); the star product of each input row is formed
-// lane-locally right before it enters the matrix cores.
-template <class Op, int N, int K, int RTI, int RTO, int P0 = 0, int P1 = 9>
+// output quantities [P0, P1) (of those the form AC carries); the star product
+// of each input row is formed lane-locally right before it enters the matrix
+// cores.
+template <class Op, int N, int K, int RTI, int RTO, bool AC, int P0 = 0, int P1 = 9>
 __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&dout)[RTO][4][9],
                                         const RefT<Op>* lds, const float* G, float lam, float mu, float rinv,
                                         int el, int g, float fk) {
@@ -444,7 +532,7 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
       // plain loop.
       auto star_of = [&](int s, float(&z)[9]) {
         const int d = s / NV, i = s % NV;
-        apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[i >> 2][i & 3], z);
+        star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[i >> 2][i & 3], z);
       };
       float zb[2][9];
       load_a(0, an[0]);
@@ -458,7 +546,8 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
           const float af = an[s & 1][mt];
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, zb[s & 1][P0 + p], acc[mt][p], 0, 0, 0);
+            if (carried<AC>(P0 + p))
+              acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, zb[s & 1][P0 + p], acc[mt][p], 0, 0, 0);
         }
         if (s + 1 < 3 * NV) star_of(s + 1, zb[(s + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
@@ -470,13 +559,13 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
         const int d = s / NV, i = s % NV, t = i >> 2, v = i & 3;
         if (s + 1 < 3 * NV) load_a(s + 1, an[(s + 1) & 1]);
         float z[9];
-        apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z);
+        star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z);
 #pragma unroll
         for (int mt = 0; mt < RTO; ++mt) {
           const float af = an[s & 1][mt];
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, z[P0 + p], acc[mt][p], 0, 0, 0);
+            if (carried<AC>(P0 + p)) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, z[P0 + p], acc[mt][p], 0, 0, 0);
         }
       }
     }
@@ -494,12 +583,13 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
           float z0[4][9], z1[4][9];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z0[v]);
-            if (two) apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[two ? t + 1 : t][v], z1[v]);
+            star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z0[v]);
+            if (two) star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[two ? t + 1 : t][v], z1[v]);
           }
           s4 b0[NP], b1[NP];
 #pragma unroll
           for (int p = 0; p < NP; ++p) {
+            if (!carried<AC>(P0 + p)) continue;
             b0[p] = pack4(z0[0][P0 + p], z0[1][P0 + p], z0[2][P0 + p], z0[3][P0 + p]);
             b1[p] = two ? pack4(z1[0][P0 + p], z1[1][P0 + p], z1[2][P0 + p], z1[3][P0 + p]) : s4{0, 0, 0, 0};
           }
@@ -509,8 +599,9 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
             const s4 a1 = two ? A.at4(16 * mt + el, 16 * (t + 1) + 4 * g) : s4{0, 0, 0, 0};
 #pragma unroll
             for (int p = 0; p < NP; ++p)
-              acc[mt][p] = two ? mfma_k32(a0, a1, b0[p], b1[p], acc[mt][p])
-                               : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0[p], acc[mt][p], 0, 0, 0);
+              if (carried<AC>(P0 + p))
+                acc[mt][p] = two ? mfma_k32(a0, a1, b0[p], b1[p], acc[mt][p])
+                                 : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0[p], acc[mt][p], 0, 0, 0);
           }
         }
         continue;
@@ -520,17 +611,18 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
         if (16 * t >= nin) continue;
         float z[4][9];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z[v]);
+        for (int v = 0; v < 4; ++v) star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z[v]);
         s4 bz[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p) bz[p] = pack4(z[0][P0 + p], z[1][P0 + p], z[2][P0 + p], z[3][P0 + p]);
+        for (int p = 0; p < NP; ++p)
+          if (carried<AC>(P0 + p)) bz[p] = pack4(z[0][P0 + p], z[1][P0 + p], z[2][P0 + p], z[3][P0 + p]);
         const int k0 = 16 * t + 4 * g;
 #pragma unroll
         for (int mt = 0; mt < RTO; ++mt) {
           const s4 af = A.at4(16 * mt + el, k0);
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bz[p], acc[mt][p], 0, 0, 0);
+            if (carried<AC>(P0 + p)) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bz[p], acc[mt][p], 0, 0, 0);
         }
       }
     }
@@ -542,14 +634,15 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * mt + 4 * v + g;
 #pragma unroll
-      for (int p = 0; p < NP; ++p) dout[mt][v][P0 + p] = row < nout ? fk * acc[mt][p][v] : 0.0f;
+      for (int p = 0; p < NP; ++p)
+        if (carried<AC>(P0 + p)) dout[mt][v][P0 + p] = row < nout ? fk * acc[mt][p][v] : 0.0f;
     }
 }
 
 // First CK step straight from Q in memory (group base Qg): the stress rows of
 // D1 read only the velocity columns of D0 and the velocity rows only the
 // stress columns, so D0 is brought in one half at a time.
-template <class Op, int N, int P0, int P1, int C0, int C1>
+template <class Op, int N, bool AC, int P0, int P1, int C0, int C1>
 __device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1))][4][9], const float* Qg,
                                               int lane, const RefT<Op>* lds, const float* G, float lam, float mu,
                                               float rinv, int el, int g, float* gd) {
@@ -563,7 +656,8 @@ __device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1
       // rows >= B are the zero padding of the tiled layout: loaded as they are,
       // so that no load sits behind a lane-dependent branch
 #pragma unroll
-      for (int p = 0; p < 9; ++p) din[t][v][p] = (p >= C0 && p < C1) ? qb.ld((t * 4 + v) * 9 + p) : 0.0f;
+      for (int p = 0; p < 9; ++p)
+        din[t][v][p] = (p >= C0 && p < C1 && carried<AC>(p)) ? qb.ld((t * 4 + v) * 9 + p) : 0.0f;
     }
   if (gd) {
 #pragma unroll
@@ -573,13 +667,13 @@ __device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1
         const int row = 16 * t + 4 * v + g;
         if (row >= B) continue;
 #pragma unroll
-        for (int p = C0; p < C1; ++p) gd[row * 9 + p] = din[t][v][p];
+        for (int p = C0; p < C1; ++p) gd[row * 9 + p] = carried<AC>(p) ? din[t][v][p] : (p < 3 ? din[t][v][0] : 0.0f);
       }
   }
-  ck_step<Op, N, 0, RT, RT1, P0, P1>(din, d1, lds, G, lam, mu, rinv, el, g, -1.0f);
+  ck_step<Op, N, 0, RT, RT1, AC, P0, P1>(din, d1, lds, G, lam, mu, rinv, el, g, -1.0f);
 }
 
-template <class Op, int N>
+template <class Op, int N, bool AC>
 struct CK {
   // J = sum_{k >= 1} Dk/(k+1) (rows below B1); I~ = Q + J.
   __device__ static __forceinline__ void run(float (&J)[row_tiles(nbasis(N - 1))][4][9], const float* Qg, int lane,
@@ -587,47 +681,48 @@ struct CK {
                              float* gd) {
     constexpr int B = nbasis(N);
     constexpr int R1 = row_tiles(nbasis(N - 1));
-    ck_first_half<Op, N, 0, 6, 6, 9>(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
+    ck_first_half<Op, N, AC, 0, 6, 6, 9>(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
     __builtin_amdgcn_sched_barrier(0);
-    ck_first_half<Op, N, 6, 9, 0, 6>(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
-    if (gd) store_deriv<N>(gd + 1 * B * 9, J, g);
+    ck_first_half<Op, N, AC, 6, 9, 0, 6>(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
+    if (gd) store_deriv<N, AC>(gd + 1 * B * 9, J, g);
 #pragma unroll
     for (int t = 0; t < R1; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int p = 0; p < 9; ++p) J[t][v][p] *= 0.5f;  // J = D1/2
+        for (int p = 0; p < 9; ++p)
+          if (carried<AC>(p)) J[t][v][p] *= 0.5f;  // J = D1/2
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (N >= 2) {
       constexpr int R2 = row_tiles(nbasis(N - 2));
       float d2[R2][4][9];
-      ck_step<Op, N, 1, R1, R2>(J, d2, lds, G, lam, mu, rinv, el, g, -1.0f);  // input D1/2
-      if (gd) store_deriv<N>(gd + 2 * B * 9, d2, g);
-      accum(J, d2, 1.0f / 3.0f);
+      ck_step<Op, N, 1, R1, R2, AC>(J, d2, lds, G, lam, mu, rinv, el, g, -1.0f);  // input D1/2
+      if (gd) store_deriv<N, AC>(gd + 2 * B * 9, d2, g);
+      accum<AC>(J, d2, 1.0f / 3.0f);
       if constexpr (N >= 3) {
         constexpr int R3 = row_tiles(nbasis(N - 3));
         float d3[R3][4][9];
-        ck_step<Op, N, 2, R2, R3>(d2, d3, lds, G, lam, mu, rinv, el, g, -1.0f / 3.0f);
-        if (gd) store_deriv<N>(gd + 3 * B * 9, d3, g);
-        accum(J, d3, 0.25f);
+        ck_step<Op, N, 2, R2, R3, AC>(d2, d3, lds, G, lam, mu, rinv, el, g, -1.0f / 3.0f);
+        if (gd) store_deriv<N, AC>(gd + 3 * B * 9, d3, g);
+        accum<AC>(J, d3, 0.25f);
         if constexpr (N >= 4) {
           constexpr int R4 = row_tiles(nbasis(N - 4));
           float d4[R4][4][9];
-          ck_step<Op, N, 3, R3, R4>(d3, d4, lds, G, lam, mu, rinv, el, g, -0.25f);
-          if (gd) store_deriv<N>(gd + 4 * B * 9, d4, g);
-          accum(J, d4, 0.2f);
+          ck_step<Op, N, 3, R3, R4, AC>(d3, d4, lds, G, lam, mu, rinv, el, g, -0.25f);
+          if (gd) store_deriv<N, AC>(gd + 4 * B * 9, d4, g);
+          accum<AC>(J, d4, 0.2f);
           if constexpr (N >= 5) {
             constexpr int R5 = row_tiles(nbasis(N - 5));
             float d5[R5][4][9];
-            ck_step<Op, N, 4, R4, R5>(d4, d5, lds, G, lam, mu, rinv, el, g, -0.2f);
-            if (gd) store_deriv<N>(gd + 5 * B * 9, d5, g);
-            accum(J, d5, 1.0f / 6.0f);
+            ck_step<Op, N, 4, R4, R5, AC>(d4, d5, lds, G, lam, mu, rinv, el, g, -0.2f);
+            if (gd) store_deriv<N, AC>(gd + 5 * B * 9, d5, g);
+            accum<AC>(J, d5, 1.0f / 6.0f);
             if constexpr (N >= 6) {
               constexpr int R6 = row_tiles(nbasis(N - 6));
               float d6[R6][4][9];
-              ck_step<Op, N, 5, R5, R6>(d5, d6, lds, G, lam, mu, rinv, el, g, -1.0f / 6.0f);
-              if (gd) store_deriv<N>(gd + 6 * B * 9, d6, g);
-              accum(J, d6, 1.0f / 7.0f);
+              ck_step<Op, N, 5, R5, R6, AC>(d5, d6, lds, G, lam, mu, rinv, el, g, -1.0f / 6.0f);
+              if (gd) store_deriv<N, AC>(gd + 6 * B * 9, d6, g);
+              accum<AC>(J, d6, 1.0f / 7.0f);
             }
           }
         }
@@ -639,7 +734,7 @@ struct CK {
 // dq[mt][p] += sum_d sum_l K^d(16 mt + el, l) (I~_l (dt A*_d)^T)_p over the rows
 // l < B1 of I~ (rows produced by rowfn from memory), each row read once for
 // all three d; software-pipelined like contract_fn.
-template <class Op, int N, class RowFn>
+template <class Op, int N, bool AC, class RowFn>
 __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const RefT<Op>* lds, RowFn rowfn,
                                        const float* G, float lam, float mu, float rinv, int el, int g) {
   using L = Lay<Op, N>;
@@ -677,15 +772,17 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
       float z[3][9];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x, z[d]);
+        star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x, z[d]);
 #pragma unroll
-        for (int p = 0; p < 9; ++p) z[d][p] = ok ? z[d][p] : 0.0f;
+        for (int p = 0; p < 9; ++p)
+          if (carried<AC>(p)) z[d][p] = ok ? z[d][p] : 0.0f;
       }
 #pragma unroll
       for (int mt = 0; mt < RT; ++mt) {
         const float a0 = an[i & 1][0][mt], a1 = an[i & 1][1][mt], a2 = an[i & 1][2][mt];
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
+          if (!carried<AC>(p)) continue;
           dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, z[0][p], dq[mt][p], 0, 0, 0);
           dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, z[1][p], dq[mt][p], 0, 0, 0);
           dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, z[2][p], dq[mt][p], 0, 0, 0);
@@ -714,24 +811,28 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const bool ok = 16 * t + 4 * v + g < B1;
-            apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x0[v], z[v]);
+            star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x0[v], z[v]);
 #pragma unroll
-            for (int p = 0; p < 9; ++p) z[v][p] = ok ? z[v][p] : 0.0f;
+            for (int p = 0; p < 9; ++p)
+              if (carried<AC>(p)) z[v][p] = ok ? z[v][p] : 0.0f;
           }
 #pragma unroll
-          for (int p = 0; p < 9; ++p) b0[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
+          for (int p = 0; p < 9; ++p)
+            if (carried<AC>(p)) b0[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
         }
         if (two) {
           float z[4][9];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const bool ok = 16 * (t + 1) + 4 * v + g < B1;
-            apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x1[v], z[v]);
+            star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, x1[v], z[v]);
 #pragma unroll
-            for (int p = 0; p < 9; ++p) z[v][p] = ok ? z[v][p] : 0.0f;
+            for (int p = 0; p < 9; ++p)
+              if (carried<AC>(p)) z[v][p] = ok ? z[v][p] : 0.0f;
           }
 #pragma unroll
-          for (int p = 0; p < 9; ++p) b1[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
+          for (int p = 0; p < 9; ++p)
+            if (carried<AC>(p)) b1[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
         }
         const View<R, L::ldK, false>& A = d == 0 ? A0 : (d == 1 ? A1 : A2);
 #pragma unroll
@@ -740,8 +841,9 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
           const s4 a1 = two ? A.at4(16 * mt + el, 16 * (t + 1) + 4 * g) : s4{0, 0, 0, 0};
 #pragma unroll
           for (int p = 0; p < 9; ++p)
-            dq[mt][p] = two ? mfma_k32(a0, a1, b0[p], b1[p], dq[mt][p])
-                            : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0[p], dq[mt][p], 0, 0, 0);
+            if (carried<AC>(p))
+              dq[mt][p] = two ? mfma_k32(a0, a1, b0[p], b1[p], dq[mt][p])
+                              : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0[p], dq[mt][p], 0, 0, 0);
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -764,19 +866,22 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const bool ok = 16 * t + 4 * v + g < B1;
-          apply_star(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, xb[t & 1][v], z[v]);
+          star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, xb[t & 1][v], z[v]);
 #pragma unroll
-          for (int p = 0; p < 9; ++p) z[v][p] = ok ? z[v][p] : 0.0f;
+          for (int p = 0; p < 9; ++p)
+            if (carried<AC>(p)) z[v][p] = ok ? z[v][p] : 0.0f;
         }
         s4 b[9];
 #pragma unroll
-        for (int p = 0; p < 9; ++p) b[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
+        for (int p = 0; p < 9; ++p)
+          if (carried<AC>(p)) b[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
         const View<R, L::ldK, false>& A = d == 0 ? A0 : (d == 1 ? A1 : A2);
 #pragma unroll
         for (int mt = 0; mt < RT; ++mt) {
           const s4 a = A.at4(16 * mt + el, k0);
 #pragma unroll
-          for (int p = 0; p < 9; ++p) dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], dq[mt][p], 0, 0, 0);
+          for (int p = 0; p < 9; ++p)
+            if (carried<AC>(p)) dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], dq[mt][p], 0, 0, 0);
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -840,196 +945,219 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
   const int el = lane & 15, g = lane >> 4;
   const int64_t gfirst = e0 >> 4, glast = (e1 - 1) >> 4;
   for (int64_t grp = gfirst + logical_block(remap) * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
-    const int64_t e = grp * 16 + el;
-    const bool live = e >= e0 && e < e1;
-    const int64_t ec = live ? e : e0;
-    // hand-over descriptors of the four faces: targets, and mode | orientation << 2 per byte
-    typedef int i4 __attribute__((ext_vector_type(4)));
-    const i4 tg4 = *reinterpret_cast<const i4*>(a.tgt + ec * 4);
-    const int mh = a.mh4[ec];
-    float G[9];
+    // one body per form: the 4-quantity form for a group of acoustic elements
+    auto body = [&](auto form) {
+      constexpr bool AC = decltype(form)::value;
+      const int64_t e = grp * 16 + el;
+      const bool live = e >= e0 && e < e1;
+      const int64_t ec = live ? e : e0;
+      // hand-over descriptors of the four faces: targets, and mode | orientation << 2 per byte
+      typedef int i4 __attribute__((ext_vector_type(4)));
+      const i4 tg4 = *reinterpret_cast<const i4*>(a.tgt + ec * 4);
+      const int mh = a.mh4[ec];
+      float G[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) G[i] = a.G[ec * 9 + i];
-    const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
-    const float* Qg = a.Q + grp * (int64_t)(RT * 36 * 64);
-    const int gs0 = a.dslot[ec];
-    const int gs = live ? gs0 : -1;
-    float* gd = gs >= 0 ? a.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
+      for (int i = 0; i < 9; ++i) G[i] = a.G[ec * 9 + i];
+      const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
+      const float* Qg = a.Q + grp * (int64_t)(RT * 36 * 64);
+      const int gs0 = a.dslot[ec];
+      const int gs = live ? gs0 : -1;
+      float* gd = gs >= 0 ? a.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
 
-    // I~ = Q + J (J = sum_{k>=1} Dk/(k+1)) is parked in memory in the same
-    // fragment layout (one coalesced access per register) so that the CK
-    // registers are free for the face and volume phases, which stream I~
-    // back (mostly from L2).
-    float* Ig = a.Ib + grp * (int64_t)(RT * 36 * 64);
-    // I~ parked in this wavefront's LDS slice (BF16) or in HBM (see PredLds)
-    constexpr bool LP = PredLds<Op, N, W>::park_lds;
-    constexpr int TF = PredLds<Op, N, W>::f32_tiles;  // FP32: leading row tiles of I~ kept in LDS
-    unsigned short* ilds = reinterpret_cast<unsigned short*>(lds_raw + L::bytes) + w * PredLds<Op, N, W>::slice;
-    float* flds = reinterpret_cast<float*>(lds_raw + L::bytes) + w * (TF * 36 * 64);
-    {
-      float J[RT1][4][9];
-      CK<Op, N>::run(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
-      // a row tile of Q is loaded before any of its stores: raw buffer
-      // accesses may alias, so a store between two loads would serialise them
-      const GroupBuf qb(Qg, RT * 36 * 256, lane), ib(Ig, RT * 36 * 256, lane);
+      // I~ = Q + J (J = sum_{k>=1} Dk/(k+1)) is parked in memory in the same
+      // fragment layout (one coalesced access per register) so that the CK
+      // registers are free for the face and volume phases, which stream I~
+      // back (mostly from L2).
+      float* Ig = a.Ib + grp * (int64_t)(RT * 36 * 64);
+      // I~ parked in this wavefront's LDS slice (BF16) or in HBM (see PredLds)
+      constexpr bool LP = PredLds<Op, N, W>::park_lds;
+      constexpr int TF = PredLds<Op, N, W>::f32_tiles;  // FP32: leading row tiles of I~ kept in LDS
+      unsigned short* ilds = reinterpret_cast<unsigned short*>(lds_raw + L::bytes) + w * PredLds<Op, N, W>::slice;
+      float* flds = reinterpret_cast<float*>(lds_raw + L::bytes) + w * (TF * 36 * 64);
+      {
+        float J[RT1][4][9];
+        CK<Op, N, AC>::run(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
+        // a row tile of Q is loaded before any of its stores: raw buffer
+        // accesses may alias, so a store between two loads would serialise them
+        const GroupBuf qb(Qg, RT * 36 * 256, lane), ib(Ig, RT * 36 * 256, lane);
 #pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        float x[36];
+        for (int t = 0; t < RT; ++t) {
+          float x[36];
 #pragma unroll
-        for (int r = 0; r < 36; ++r) x[r] = qb.ld(t * 36 + r);  // zero on the padding rows
+          for (int r = 0; r < 36; ++r)
+            if (carried<AC>(r % 9)) x[r] = qb.ld(t * 36 + r);  // zero on the padding rows
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+          for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int p = 0; p < 9; ++p) {
+              if (!carried<AC>(p)) continue;
+              float y = x[v * 9 + p];
+              if (t < RT1) y += J[t < RT1 ? t : 0][v][p];
+              if constexpr (LP)
+                ilds[((t * 4 + v) * 9 + p) * 64 + lane] = f2bf_dev(y);
+              else if (t < TF)
+                flds[((t * 4 + v) * 9 + p) * 64 + lane] = y;
+              else
+                ib.st((t * 4 + v) * 9 + p, y);
+            }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+
+      f4 dq[RT][9];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int p = 0; p < 9; ++p)
+          if (carried<AC>(p)) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
+
+      // rows of I~, read through a laundered base (one per contraction, so the
+      // reads are not merged across contractions and kept live)
+      auto itil_at = [&](const float* ip) {
+        const GroupBuf ib(ip, RT * 36 * 256, lane);
+        const float* fl = flds + opaque_zero();
+        return [=](int t, int v, float (&b)[9]) {
 #pragma unroll
           for (int p = 0; p < 9; ++p) {
-            float y = x[v * 9 + p];
-            if (t < RT1) y += J[t < RT1 ? t : 0][v][p];
+            if (!carried<AC>(p)) continue;
             if constexpr (LP)
-              ilds[((t * 4 + v) * 9 + p) * 64 + lane] = f2bf_dev(y);
+              b[p] = __uint_as_float((unsigned)ilds[((t * 4 + v) * 9 + p) * 64 + lane] << 16);
             else if (t < TF)
-              flds[((t * 4 + v) * 9 + p) * 64 + lane] = y;
+              b[p] = fl[((t * 4 + v) * 9 + p) * 64 + lane];
             else
-              ib.st((t * 4 + v) * 9 + p, y);
+              b[p] = ib.ld((t * 4 + v) * 9 + p);
           }
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-
-    f4 dq[RT][9];
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
-
-    // rows of I~, read through a laundered base (one per contraction, so the
-    // reads are not merged across contractions and kept live)
-    auto itil_at = [&](const float* ip) {
-      const GroupBuf ib(ip, RT * 36 * 256, lane);
-      const float* fl = flds + opaque_zero();
-      return [=](int t, int v, float (&b)[9]) {
-#pragma unroll
-        for (int p = 0; p < 9; ++p) {
-          if constexpr (LP)
-            b[p] = __uint_as_float((unsigned)ilds[((t * 4 + v) * 9 + p) * 64 + lane] << 16);
-          else if (t < TF)
-            b[p] = fl[((t * 4 + v) * 9 + p) * 64 + lane];
-          else
-            b[p] = ib.ld((t * 4 + v) * 9 + p);
-        }
+        };
       };
-    };
 
-    // faces: traces at the nodes, hand-over, own-trace flux, lift. A real
-    // loop: unrolled, the four faces' live ranges overlap and spill.
+      // faces: traces at the nodes, hand-over, own-trace flux, lift. A real
+      // loop: unrolled, the four faces' live ranges overlap and spill.
 #pragma unroll 1
-    for (int f = 0; f < 4; ++f) {
-      // this face's flux coefficients, requested before the trace products
-      float c[11];
+      for (int f = 0; f < 4; ++f) {
+        // this face's flux coefficients, requested before the trace products
+        float c[11];
 #pragma unroll
-      for (int i = 0; i < 11; ++i) c[i] = a.RCm[(ec * 4 + f) * 12 + i];
-      f4 va[FT][9];
+        for (int i = 0; i < 11; ++i) c[i] = a.RCm[(ec * 4 + f) * 12 + i];
+        f4 va[FT][9];
 #pragma unroll
-      for (int t = 0; t < FT; ++t)
+        for (int t = 0; t < FT; ++t)
 #pragma unroll
-        for (int p = 0; p < 9; ++p) va[t][p] = f4{0.f, 0.f, 0.f, 0.f};
-      const View<R, L::ldE, false> AE(lds + L::oE + f * 16 * FT * L::ldE);
-      contract_fn<Op, View<R, L::ldE, false>, RT, FT, true>(va, AE, B, el, g, itil_at(Ig));
-      float V[FT][4][9];
-#pragma unroll
-      for (int t = 0; t < FT; ++t)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const bool ok = 16 * t + 4 * v + g < Bf;  // node in slot (t, g, v)
-#pragma unroll
-          for (int p = 0; p < 9; ++p) V[t][v][p] = ok ? va[t][p][v] : 0.0f;
-        }
-      // hand-over into the neighbour's inbox (its node numbering, its time
-      // step): a neighbour in the same cluster gets the full-step trace; a
-      // coarser one half of it, accumulated over this element's two steps
-      // (the parity of the step is per element: a launch may span clusters);
-      // a finer one gets the full-step
-      // trace here, which the half-step fix-up turns into its two halves.
-      // Loads are unconditional (valid indices for every lane); only the
-      // stores are masked.
-      {
-        const int md0 = (mh >> (8 * f)) & 3;
-        const int32_t tg0 = f == 0 ? tg4[0] : (f == 1 ? tg4[1] : (f == 2 ? tg4[2] : tg4[3]));
-        const int h = (mh >> (8 * f + 2)) & 7;
-        const bool send = live && md0 != 0;
-        const bool half = md0 == 3;
-        const int parity = sc.parity(ec);
-        const int32_t tg = send ? tg0 : 0;
+          for (int p = 0; p < 9; ++p)
+            if (carried<AC>(p)) va[t][p] = f4{0.f, 0.f, 0.f, 0.f};
+        const View<R, L::ldE, false> AE(lds + L::oE + f * 16 * FT * L::ldE);
+        contract_fn<Op, View<R, L::ldE, false>, RT, FT, true, false, AC>(va, AE, B, el, g, itil_at(Ig));
+        float V[FT][4][9];
 #pragma unroll
         for (int t = 0; t < FT; ++t)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int node = 16 * t + 4 * v + g;
-            const int mr = perm[h * Bf + (node < Bf ? node : Bf - 1)];
-            if (!send || node >= Bf) continue;
-            float* blk = a.In + in_block(tg >> 2, tg & 3, mr, FT) * 576;
-            const int l = in_lane(tg >> 2, mr);
-            if (half && parity) {
-              // second step of the pair: add to the first half (one writer per
-              // slot; a no-return atomic keeps the load out of this kernel)
+            const bool ok = 16 * t + 4 * v + g < Bf;  // node in slot (t, g, v)
 #pragma unroll
-              for (int p = 0; p < 8; ++p) atomicAdd(blk + 8 * l + p, 0.5f * V[t][v][p]);
-              atomicAdd(blk + 512 + l, 0.5f * V[t][v][8]);
-            } else {
-              const float s = half ? 0.5f : 1.0f;
-              f4* d8 = reinterpret_cast<f4*>(blk + 8 * l);
-              d8[0] = f4{s * V[t][v][0], s * V[t][v][1], s * V[t][v][2], s * V[t][v][3]};
-              d8[1] = f4{s * V[t][v][4], s * V[t][v][5], s * V[t][v][6], s * V[t][v][7]};
-              blk[512 + l] = s * V[t][v][8];
-            }
+            for (int p = 0; p < 9; ++p)
+              if (carried<AC>(p)) V[t][v][p] = ok ? va[t][p][v] : 0.0f;
+            embed<AC>(V[t][v]);  // the neighbour reads nine quantities
           }
-      }
+        // hand-over into the neighbour's inbox (its node numbering, its time
+        // step): a neighbour in the same cluster gets the full-step trace; a
+        // coarser one half of it, accumulated over this element's two steps
+        // (the parity of the step is per element: a launch may span clusters);
+        // a finer one gets the full-step
+        // trace here, which the half-step fix-up turns into its two halves.
+        // Loads are unconditional (valid indices for every lane); only the
+        // stores are masked.
+        {
+          const int md0 = (mh >> (8 * f)) & 3;
+          const int32_t tg0 = f == 0 ? tg4[0] : (f == 1 ? tg4[1] : (f == 2 ? tg4[2] : tg4[3]));
+          const int h = (mh >> (8 * f + 2)) & 7;
+          const bool send = live && md0 != 0;
+          const bool half = md0 == 3;
+          const int parity = sc.parity(ec);
+          const int32_t tg = send ? tg0 : 0;
 #pragma unroll
-      for (int t = 0; t < FT; ++t)
+          for (int t = 0; t < FT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float out[9];
-          node_flux(c, lam, mu, rinv, V[t][v], out);
+            for (int v = 0; v < 4; ++v) {
+              const int node = 16 * t + 4 * v + g;
+              const int mr = perm[h * Bf + (node < Bf ? node : Bf - 1)];
+              if (!send || node >= Bf) continue;
+              float* blk = a.In + in_block(tg >> 2, tg & 3, mr, FT) * 576;
+              const int l = in_lane(tg >> 2, mr);
+              if (half && parity) {
+                // second step of the pair: add to the first half (one writer per
+                // slot; a no-return atomic keeps the load out of this kernel)
 #pragma unroll
-          for (int p = 0; p < 9; ++p) V[t][v][p] = out[p];
+                for (int p = 0; p < 8; ++p) atomicAdd(blk + 8 * l + p, 0.5f * V[t][v][p]);
+                atomicAdd(blk + 512 + l, 0.5f * V[t][v][8]);
+              } else {
+                const float s = half ? 0.5f : 1.0f;
+                f4* d8 = reinterpret_cast<f4*>(blk + 8 * l);
+                d8[0] = f4{s * V[t][v][0], s * V[t][v][1], s * V[t][v][2], s * V[t][v][3]};
+                d8[1] = f4{s * V[t][v][4], s * V[t][v][5], s * V[t][v][6], s * V[t][v][7]};
+                blk[512 + l] = s * V[t][v][8];
+              }
+            }
         }
-      const View<R, L::ldL, false> AL(lds + L::oL + f * L::PB * L::ldL);
-      contract_fn<Op, View<R, L::ldL, false>, FT, RT, false, true>(dq, AL, Bf, el, g,
-                                                      [&](int t, int v, float (&b)[9]) {
 #pragma unroll
-                                                        for (int p = 0; p < 9; ++p) b[p] = V[t][v][p];
-                                                      });
-    }
-
-    // volume: dq += sum_d K^d (I~ (dt A*_d)^T) over the rows of I~ below B1,
-    // the three directions from one pass over I~
-    volume<Op, N>(dq, lds, itil_at(Ig), G, lam, mu, rinv, el, g);
-    __builtin_amdgcn_sched_barrier(0);
-
-    {
-      // Q += dq for live elements and rows below B
-      // QB row tiles are requested before the first of their stores (raw
-      // buffer accesses may alias, so a store orders later loads behind it):
-      // one memory latency per QB tiles. All four tiles at order 6 in BF16;
-      // two where registers are tighter.
-      constexpr int QB = (L::BF && RT <= 4) ? RT : 2;
-      const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
-#pragma unroll
-      for (int t0 = 0; t0 < RT; t0 += QB) {
-        float q[QB][36];
-#pragma unroll
-        for (int u = 0; u < QB; ++u)
-#pragma unroll
-          for (int r = 0; r < 36; ++r) q[u][r] = t0 + u < RT ? qb.ld((t0 + u) * 36 + r) : 0.0f;
-#pragma unroll
-        for (int u = 0; u < QB; ++u)
+        for (int t = 0; t < FT; ++t)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int t = t0 + u;
-            if (t >= RT || !live || 16 * t + 4 * v + g >= B) continue;
+            float out[9];
+            node_flux_q<AC, AC>(c, lam, mu, rinv, V[t][v], out);
 #pragma unroll
-            for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[u][v * 9 + p] + dq[t < RT ? t : 0][p][v]);
+            for (int p = 0; p < 9; ++p)
+              if (carried<AC>(p)) V[t][v][p] = out[p];
           }
+        const View<R, L::ldL, false> AL(lds + L::oL + f * L::PB * L::ldL);
+        contract_fn<Op, View<R, L::ldL, false>, FT, RT, false, true, AC>(dq, AL, Bf, el, g,
+                                                            [&](int t, int v, float (&b)[9]) {
+#pragma unroll
+                                                              for (int p = 0; p < 9; ++p)
+                                                                if (carried<AC>(p)) b[p] = V[t][v][p];
+                                                            });
       }
-    }
+
+      // volume: dq += sum_d K^d (I~ (dt A*_d)^T) over the rows of I~ below B1,
+      // the three directions from one pass over I~
+      volume<Op, N, AC>(dq, lds, itil_at(Ig), G, lam, mu, rinv, el, g);
+      __builtin_amdgcn_sched_barrier(0);
+
+      {
+        // Q += dq for live elements and rows below B
+        // QB row tiles are requested before the first of their stores (raw
+        // buffer accesses may alias, so a store orders later loads behind it):
+        // one memory latency per QB tiles. All four tiles at order 6 in BF16;
+        // two where registers are tighter.
+        constexpr int QB = (L::BF && RT <= 4) ? RT : 2;
+        const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
+#pragma unroll
+        for (int t0 = 0; t0 < RT; t0 += QB) {
+          float q[QB][36];
+#pragma unroll
+          for (int u = 0; u < QB; ++u)
+#pragma unroll
+            for (int r = 0; r < 36; ++r)
+              if (carried<AC>(r % 9)) q[u][r] = t0 + u < RT ? qb.ld((t0 + u) * 36 + r) : 0.0f;
+#pragma unroll
+          for (int u = 0; u < QB; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int t = t0 + u;
+              if (t >= RT || !live || 16 * t + 4 * v + g >= B) continue;
+              float y[9];
+#pragma unroll
+              for (int p = 0; p < 9; ++p)
+                if (carried<AC>(p)) y[p] = q[u][v * 9 + p] + dq[t < RT ? t : 0][p][v];
+              embed<AC>(y);  // the 4-quantity form stores s_yy = s_zz = s_xx and zero shear
+#pragma unroll
+              for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, y[p]);
+            }
+        }
+      }
+    };
+    if (__builtin_amdgcn_readfirstlane(a.gac[grp]))
+      body(std::true_type{});
+    else
+      body(std::false_type{});
   }
 }
 
@@ -1063,99 +1191,114 @@ __global__ __launch_bounds__(64 * W, (SPLIT >= 2 && N <= 5) ? 2 : 1) void k_corr
   const int el = lane & 15, g = lane >> 4;
   const int64_t gfirst = e0 >> 4, glast = (e1 - 1) >> 4;
   for (int64_t grp = gfirst + logical_block(remap) * W + w; grp <= glast; grp += (int64_t)gridDim.x * W) {
-    const int64_t e = grp * 16 + el;
-    const bool live = e >= e0 && e < e1;
-    const int64_t ec = live ? e : e0;
-    const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
+    auto body = [&](auto form) {
+      constexpr bool AC = decltype(form)::value;
+      const int64_t e = grp * 16 + el;
+      const bool live = e >= e0 && e < e1;
+      const int64_t ec = live ? e : e0;
+      const float lam = a.mat[ec * 3 + 0], mu = a.mat[ec * 3 + 1], rinv = a.mat[ec * 3 + 2];
 #pragma unroll
-    for (int h = 0; h < NS; ++h) {
-      const int t0 = h * MH;
-      f4 dq[MH][9];
+      for (int h = 0; h < NS; ++h) {
+        const int t0 = h * MH;
+        f4 dq[MH][9];
 #pragma unroll
-      for (int t = 0; t < MH; ++t)
+        for (int t = 0; t < MH; ++t)
 #pragma unroll
-        for (int p = 0; p < 9; ++p) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
-      // the (face, node tile) steps are software-pipelined: the inbox traces
-      // of step s + CD are requested while step s computes its Riemann fluxes
-      // and its rows of the lift (one scheduling region per step, so the
-      // requests are not sunk to their use)
-      constexpr int NSTEP = 4 * FT;
-      const float* inb = a.In + grp * 4 * (int64_t)(FT * 4 * 576);
-      auto load_step = [&](int s, float(&dst)[4][9]) {
-        const float* blk0 = inb + s * (4 * 576);  // face s / FT, tile s % FT
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float* blk = blk0 + v * 576;
-          const f4 i0 = reinterpret_cast<const f4*>(blk + 8 * lane)[0];
-          const f4 i1 = reinterpret_cast<const f4*>(blk + 8 * lane)[1];
-#pragma unroll
-          for (int p = 0; p < 4; ++p) {
-            dst[v][p] = i0[p];
-            dst[v][4 + p] = i1[p];
-          }
-          dst[v][8] = blk[512 + lane];
-        }
-      };
-      // flux coefficients of the current face and the next (requested one
-      // step before the next face starts)
-      float c[2][11];
-#pragma unroll
-      for (int i = 0; i < 11; ++i) c[0][i] = a.RCp[(ec * 4) * 12 + i];
-      float tb[CD + 1][4][9];
-#pragma unroll
-      for (int s = 0; s < CD; ++s) load_step(s, tb[s]);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int s = 0; s < NSTEP; ++s) {
-        const int f = s / FT, t = s % FT;
-        if (s + CD < NSTEP) load_step(s + CD, tb[(s + CD) % (CD + 1)]);
-        if (t == FT - 1 && f + 1 < 4) {
-#pragma unroll
-          for (int i = 0; i < 11; ++i) c[(f + 1) & 1][i] = a.RCp[(ec * 4 + f + 1) * 12 + i];
-        }
-        float(&cur)[4][9] = tb[s % (CD + 1)];
-        float V[4][9];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float out[9];
-          node_flux(c[f & 1], lam, mu, rinv, cur[v], out);
-          const bool ok = 16 * t + 4 * v + g < Bf;  // node in slot (t, g, v)
-#pragma unroll
-          for (int p = 0; p < 9; ++p) V[v][p] = ok ? out[p] : 0.0f;
-        }
-        const View<R, L::ldL, false> AL(ldsL + f * L::PB * L::ldL + t0 * 16 * L::ldL + 16 * t);
-        contract_fn<Op, View<R, L::ldL, false>, 1, MH, false, true>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el, g,
-                                                       [&](int, int v, float (&b)[9]) {
-#pragma unroll
-                                                         for (int p = 0; p < 9; ++p) b[p] = V[v][p];
-                                                       });
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      // up to four of the pass's row tiles are requested before their stores
-      // (raw buffer accesses may alias): one memory latency per batch; one
-      // tile at a time in the two-pass form, whose registers must leave room
-      // for two wavefronts per SIMD
-      constexpr int QB = SPLIT >= 2 ? 1 : (MH < 4 ? MH : 4);
-      const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
-#pragma unroll
-      for (int u0 = 0; u0 < MH; u0 += QB) {
-        float q[QB][36];
-#pragma unroll
-        for (int u = 0; u < QB; ++u)
-#pragma unroll
-          for (int r = 0; r < 36; ++r)
-            q[u][r] = (u0 + u < MH && t0 + u0 + u < RT) ? qb.ld((t0 + u0 + u) * 36 + r) : 0.0f;
-#pragma unroll
-        for (int u = 0; u < QB; ++u)
+          for (int p = 0; p < 9; ++p)
+            if (carried<AC>(p)) dq[t][p] = f4{0.f, 0.f, 0.f, 0.f};
+        // the (face, node tile) steps are software-pipelined: the inbox traces
+        // of step s + CD are requested while step s computes its Riemann fluxes
+        // and its rows of the lift (one scheduling region per step, so the
+        // requests are not sunk to their use)
+        constexpr int NSTEP = 4 * FT;
+        const float* inb = a.In + grp * 4 * (int64_t)(FT * 4 * 576);
+        auto load_step = [&](int s, float(&dst)[4][9]) {
+          const float* blk0 = inb + s * (4 * 576);  // face s / FT, tile s % FT
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int uu = u0 + u, t = t0 + uu;
-            if (uu >= MH || t >= RT || !live || 16 * t + 4 * v + g >= B) continue;
+            const float* blk = blk0 + v * 576;
+            const f4 i0 = reinterpret_cast<const f4*>(blk + 8 * lane)[0];
+            const f4 i1 = reinterpret_cast<const f4*>(blk + 8 * lane)[1];
 #pragma unroll
-            for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, q[u][v * 9 + p] + dq[uu < MH ? uu : 0][p][v]);
+            for (int p = 0; p < 4; ++p) {
+              dst[v][p] = i0[p];
+              dst[v][4 + p] = i1[p];
+            }
+            dst[v][8] = blk[512 + lane];
           }
+        };
+        // flux coefficients of the current face and the next (requested one
+        // step before the next face starts)
+        float c[2][11];
+#pragma unroll
+        for (int i = 0; i < 11; ++i) c[0][i] = a.RCp[(ec * 4) * 12 + i];
+        float tb[CD + 1][4][9];
+#pragma unroll
+        for (int s = 0; s < CD; ++s) load_step(s, tb[s]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < NSTEP; ++s) {
+          const int f = s / FT, t = s % FT;
+          if (s + CD < NSTEP) load_step(s + CD, tb[(s + CD) % (CD + 1)]);
+          if (t == FT - 1 && f + 1 < 4) {
+#pragma unroll
+            for (int i = 0; i < 11; ++i) c[(f + 1) & 1][i] = a.RCp[(ec * 4 + f + 1) * 12 + i];
+          }
+          float(&cur)[4][9] = tb[s % (CD + 1)];
+          float V[4][9];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float out[9];
+            node_flux_q<AC, false>(c[f & 1], lam, mu, rinv, cur[v], out);  // the neighbour's trace has nine quantities
+            const bool ok = 16 * t + 4 * v + g < Bf;  // node in slot (t, g, v)
+#pragma unroll
+            for (int p = 0; p < 9; ++p)
+              if (carried<AC>(p)) V[v][p] = ok ? out[p] : 0.0f;
+          }
+          const View<R, L::ldL, false> AL(ldsL + f * L::PB * L::ldL + t0 * 16 * L::ldL + 16 * t);
+          contract_fn<Op, View<R, L::ldL, false>, 1, MH, false, true, AC>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el,
+                                                                      g, [&](int, int v, float (&b)[9]) {
+#pragma unroll
+                                                                        for (int p = 0; p < 9; ++p)
+                                                                          if (carried<AC>(p)) b[p] = V[v][p];
+                                                                      });
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        // up to four of the pass's row tiles are requested before their stores
+        // (raw buffer accesses may alias): one memory latency per batch; one
+        // tile at a time in the two-pass form, whose registers must leave room
+        // for two wavefronts per SIMD
+        constexpr int QB = SPLIT >= 2 ? 1 : (MH < 4 ? MH : 4);
+        const GroupBuf qb(a.Q + grp * (int64_t)(RT * 36 * 64), RT * 36 * 256, lane);
+#pragma unroll
+        for (int u0 = 0; u0 < MH; u0 += QB) {
+          float q[QB][36];
+#pragma unroll
+          for (int u = 0; u < QB; ++u)
+#pragma unroll
+            for (int r = 0; r < 36; ++r)
+              if (carried<AC>(r % 9)) q[u][r] = (u0 + u < MH && t0 + u0 + u < RT) ? qb.ld((t0 + u0 + u) * 36 + r) : 0.0f;
+#pragma unroll
+          for (int u = 0; u < QB; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int uu = u0 + u, t = t0 + uu;
+              if (uu >= MH || t >= RT || !live || 16 * t + 4 * v + g >= B) continue;
+              float y[9];
+#pragma unroll
+              for (int p = 0; p < 9; ++p)
+                if (carried<AC>(p)) y[p] = q[u][v * 9 + p] + dq[uu < MH ? uu : 0][p][v];
+              embed<AC>(y);
+#pragma unroll
+              for (int p = 0; p < 9; ++p) qb.st((t * 4 + v) * 9 + p, y[p]);
+            }
+        }
       }
-    }
+    };
+    if (__builtin_amdgcn_readfirstlane(a.gac[grp]))
+      body(std::true_type{});
+    else
+      body(std::false_type{});
   }
 }
 

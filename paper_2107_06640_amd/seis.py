@@ -46,7 +46,7 @@ class Materials_t(C.Structure):
 class Options_t(C.Structure):
     _fields_ = [("precision", C.c_int), ("kernel", C.c_int), ("cfl", C.c_double), ("g", C.c_double),
                 ("max_clusters", C.c_int), ("stream", C.c_void_p), ("tile", C.c_int), ("graph", C.c_int),
-                ("mc_min", C.c_int), ("fused", C.c_int)]
+                ("mc_min", C.c_int), ("fused", C.c_int), ("acoustic", C.c_int)]
 
 
 class Info_t(C.Structure):
@@ -55,7 +55,7 @@ class Info_t(C.Structure):
                 ("n_elements", C.c_int64), ("n_gravity_faces", C.c_int64), ("dt_min", C.c_double),
                 ("time", C.c_double), ("cluster_size", C.c_int64 * 16), ("updates_per_macro_step", C.c_int64),
                 ("device_bytes", C.c_int64), ("launch", C.c_int * 8), ("launch_source", C.c_int),
-                ("fused", C.c_int), ("shape", C.c_int)]
+                ("fused", C.c_int), ("shape", C.c_int), ("n_acoustic_groups", C.c_int64)]
 
 
 _lib = None
@@ -123,7 +123,7 @@ class Solver:
 
     def __init__(self, xyz, tet, face_kind, period, rho, lam, mu, order, *, precision="fp64",
                  kernel="tuned", cfl=0.35, g=9.81, max_clusters=1, stream=None, tile=0, graph=False,
-                 mc_min=None, fused=True):
+                 mc_min=None, fused=True, acoustic=True):
         lib = load_library()
         self._lib = lib
         self._keep = [np.ascontiguousarray(xyz, dtype=np.float64), np.ascontiguousarray(tet, dtype=np.int64),
@@ -146,6 +146,7 @@ class Solver:
         if mc_min is not None:
             opt.mc_min = int(mc_min)
         opt.fused = 1 if fused else 0
+        opt.acoustic = 1 if acoustic else 0
         h = C.c_void_p()
         rc = lib.seis_setup(C.byref(mesh), C.byref(mats), int(order), C.byref(opt), C.byref(h))
         if rc != 0:

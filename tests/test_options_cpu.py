@@ -40,3 +40,4 @@ def test_default_options():
     assert opt.precision == 0 and opt.kernel == 0 and opt.max_clusters == 1
     assert abs(opt.cfl - 0.35) < 1e-15 and abs(opt.g - 9.81) < 1e-15
     assert opt.tile == 0 and opt.graph == 0 and opt.mc_min == 2048
+    assert opt.fused == 1 and opt.acoustic == 1
