@@ -8,8 +8,9 @@ element). Either orientation is accepted; volumes use |det J|. Face i is the
 face opposite local vertex i and is parametrised by its vertices in ascending
 local order: x = X_f0 + s (X_f1 - X_f0) + t (X_f2 - X_f0).
 
-Interior faces are matched by their sorted global vertex triples; periodic
-faces by their centroids modulo the box period.
+Interior faces (and the two sides of a dynamic-rupture fault face, kind 7)
+are matched by their sorted global vertex triples; periodic faces by their
+centroids modulo the box period.
 """
 from __future__ import annotations
 
@@ -82,8 +83,8 @@ def adjacency(tet, face_kind, xyz, period):
     nb = -np.ones((E, 4), dtype=np.int64)
     nbf = -np.ones((E, 4), dtype=np.int64)
     shift = np.zeros((E, 4, 3))
-    # interior faces: sort the sorted vertex triples; a matched face is a run of two
-    ee, ff = np.nonzero(face_kind == 0)
+    # interior and fault faces: sort the sorted vertex triples; a matched face is a run of two
+    ee, ff = np.nonzero((face_kind == 0) | (face_kind == 7))
     if ee.size:
         keys = np.sort(tet[ee[:, None], np.array(FACE_VERTS)[ff]], axis=1)
         order = np.lexsort((keys[:, 2], keys[:, 1], keys[:, 0]))
@@ -92,6 +93,8 @@ def adjacency(tet, face_kind, xyz, period):
         if 2 * pair.size != ee.size or np.any(np.diff(pair) < 2):
             raise ValueError("interior faces without exactly one neighbour")
         a, b = order[pair], order[pair + 1]
+        if np.any(face_kind[ee[a], ff[a]] != face_kind[ee[b], ff[b]]):
+            raise ValueError("a fault face must meet a fault face")
         nb[ee[a], ff[a]], nbf[ee[a], ff[a]] = ee[b], ff[b]
         nb[ee[b], ff[b]], nbf[ee[b], ff[b]] = ee[a], ff[a]
     # periodic faces: match centroids modulo the period

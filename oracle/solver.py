@@ -38,8 +38,9 @@ from . import quadrature as quad
 from .mesh import Geometry, adjacency, ref_face_points, FACE_VERTS
 from .physics import jacobians, stress_tensor
 from .riemann import godunov_flux, ghost_state, gravity_eta_step, flux_of_state
+from .fault import N_PARAMS, fault_state
 
-FACE_INTERIOR, FACE_PERIODIC, FACE_GRAVITY, FACE_ABSORBING, FACE_WALL, FACE_FREE, FACE_VELOCITY = range(7)
+FACE_INTERIOR, FACE_PERIODIC, FACE_GRAVITY, FACE_ABSORBING, FACE_WALL, FACE_FREE, FACE_VELOCITY, FACE_FAULT = range(8)
 
 
 def uplift(sources, x, y, t):
@@ -65,16 +66,22 @@ def taylor_weights(N: int, a: float, b: float) -> np.ndarray:
     return np.array([(b ** (k + 1) - a ** (k + 1)) / math.factorial(k + 1) for k in range(N + 1)])
 
 
-def assign_clusters(dt_elem, nb, max_clusters):
-    """Rate-2 clustering (Sec. 4.4) with the neighbour-difference rule."""
+def assign_clusters(dt_elem, nb, max_clusters, tied=None):
+    """Rate-2 clustering (Sec. 4.4) with the neighbour-difference rule.
+
+    ``tied`` [E, 4] marks faces whose two elements must share a cluster (the
+    two sides of a fault face, which the friction law couples pointwise in
+    time): across them the rule is c_K <= c_J instead of c_K <= c_J + 1.
+    """
     dt_min = float(dt_elem.min())
     c = np.floor(np.log2(dt_elem / dt_min)).astype(np.int64)
     c = np.clip(c, 0, max_clusters - 1)
+    step = np.ones(nb.shape, dtype=np.int64) if tied is None else np.where(tied, 0, 1)
     # lower c_K to c_J + 1 wherever a face neighbour J is more than one cluster
     # finer, until nothing changes (the largest assignment obeying the rule)
     while True:
-        nbc = np.where(nb >= 0, c[np.maximum(nb, 0)], max_clusters)
-        low = np.minimum(c, nbc.min(axis=1) + 1)
+        nbc = np.where(nb >= 0, c[np.maximum(nb, 0)] + step, max_clusters + 1)
+        low = np.minimum(c, nbc.min(axis=1))
         if np.array_equal(low, c):
             break
         c = low
@@ -123,7 +130,8 @@ class Oracle:
         # time steps and clusters (Sec. 4.4)
         self.dt_elem = cfl / (2 * N + 1) * self.geo.h / self.cp
         if cluster_of is None:
-            self.cluster, self.dt_min = assign_clusters(self.dt_elem, self.nb, max_clusters)
+            self.cluster, self.dt_min = assign_clusters(self.dt_elem, self.nb, max_clusters,
+                                                        tied=self.face_kind == FACE_FAULT)
         else:
             self.cluster = np.asarray(cluster_of, dtype=np.int64)
             self.dt_min = float(self.dt_elem.min())
@@ -143,6 +151,8 @@ class Oracle:
             raise ValueError("gravity face on an elastic element")
         self.eta = np.zeros((ge.size, self.gst.shape[0]))
 
+        self._init_faults()
+
         self.Q = np.zeros((E, self.B, 9))
         self.uplift_sources = []
         self._nb_cache = {}
@@ -150,6 +160,122 @@ class Oracle:
         self.updates = 0
 
     # ------------------------------------------------------------------
+    def _init_faults(self):
+        """Dynamic-rupture faces (Sec. 3, fault boundary condition).
+
+        A fault face is listed once, from its '-' side: the element with the
+        smaller index. Its points are the equispaced lattice of degree N on
+        the '-' face (face parameters (j/N, k/N)), where the friction law is
+        applied; the flux there is interpolated on the face by the degree-N
+        polynomial through those points. The fault starts locked (infinite
+        cohesion) until set_fault gives it parameters.
+        """
+        N = self.N
+        fe, ff = np.nonzero(self.face_kind == FACE_FAULT)
+        minus = fe < self.nb[fe, ff]
+        fe, ff = fe[minus], ff[minus]
+        pe, pf = self.nb[fe, ff], self.nbf[fe, ff]
+        if fe.size and (np.any(self.mu[fe] <= 0) or np.any(self.mu[pe] <= 0)):
+            raise ValueError("a fault face needs elastic elements on both sides")
+        if fe.size and np.any(self.cluster[fe] != self.cluster[pe]):
+            raise ValueError("the two sides of a fault face are in different clusters")
+        self.fault_elem, self.fault_face = fe, ff
+        self.fault_pelem, self.fault_pface = pe, pf
+        lat = np.array([(j / N, k / N) for j in range(N + 1) for k in range(N + 1 - j)])
+        self.fault_lattice = lat
+        self.fault_points = self.geo.face_points(fe, ff, lat)            # [F, nf, 3]
+        # interpolation of nodal values to the flux points of either side, in
+        # the '-' face's parameters (monomials s^a t^b, a + b <= N)
+        pw = [(a, b) for a in range(N + 1) for b in range(N + 1 - a)]
+        vander = lambda st: np.stack([st[..., 0] ** a * st[..., 1] ** b for a, b in pw], axis=-1)
+        Vinv = np.linalg.inv(vander(lat))
+        nF = fe.size
+        self.fault_Lm = np.broadcast_to(vander(self.fst) @ Vinv, (nF,) + (self.fst.shape[0], lat.shape[0])).copy()
+        xp = self.geo.face_points(pe, pf, self.fst)                        # '+' side flux points
+        X = self.geo.X
+        fv = np.array(FACE_VERTS)[ff]
+        P0 = X[fe, fv[:, 0]]
+        U = np.stack([X[fe, fv[:, 1]] - P0, X[fe, fv[:, 2]] - P0], axis=2)  # [F, 3, 2]
+        stp = np.einsum("fij,fqj->fqi", np.linalg.pinv(U), xp - P0[:, None, :])
+        self.fault_Lp = vander(stp) @ Vinv
+        self.fault_params = np.zeros((nF, N_PARAMS))
+        self.fault_params[:, 6] = 1.0
+        self.fault_params[:, 7] = np.inf
+        nf = lat.shape[0]
+        self.fault_slip = np.zeros((nF, nf, 3))
+        self.fault_psi = np.zeros((nF, nf))
+        self.fault_rate = np.zeros((nF, nf, 3))
+        self.fault_traction = np.zeros((nF, nf, 3))
+        self.fault_normal = np.zeros((nF, nf))
+
+    def set_fault(self, params):
+        """Fault parameters [F, 8] per face: s0, tau0 (3), mu_s, mu_d, D_c, C."""
+        p = np.asarray(params, dtype=np.float64)
+        self.fault_params[:] = np.broadcast_to(p, self.fault_params.shape)
+
+    def _fault_fluxes(self, c, own, dt):
+        """Face-flux updates of the fault faces of cluster c over its step of length dt.
+
+        Returns (element ids, local faces, dQ contributions) for both sides.
+        """
+        sel = np.nonzero(self.cluster[self.fault_elem] == c)[0]
+        if not sel.size:
+            return []
+        N = self.N
+        xg, wg = np.polynomial.legendre.leggauss(N + 1)
+        tj = 0.5 * dt * (xg + 1.0)
+        wj = 0.5 * dt * wg
+        fact = np.array([math.factorial(k) for k in range(N + 1)], dtype=np.float64)
+        out = []
+        fe, ff, pe, pf = (a[sel] for a in (self.fault_elem, self.fault_face, self.fault_pelem, self.fault_pface))
+        x = self.fault_points[sel]                                           # [m, nf, 3]
+        n = self.geo.normal[fe, ff][:, None, :] * np.ones((1, x.shape[1], 1))
+        # traces of the time derivatives at the lattice points: [m, N+1, nf, 9]
+        tr = []
+        for e in (fe, pe):
+            # the lattice includes the face's vertices: the closed form of the basis is regular there
+            phi = bas.eval_basis_closed(N, self.geo.to_ref(e[:, None], x).reshape(-1, 3)).reshape(e.size, -1, self.B)
+            tr.append(ein("mqb,mkbp->mkqp", phi, own[self.pos[e]]))
+        one = np.ones(x.shape[1])
+        matm = tuple(a[fe][:, None] * one for a in (self.lam, self.mu, self.rho))
+        matp = tuple(a[pe][:, None] * one for a in (self.lam, self.mu, self.rho))
+        prm = self.fault_params[sel][:, None, :] * np.ones((1, x.shape[1], 1))
+        psi = self.fault_psi[sel].copy()
+        slip = self.fault_slip[sel].copy()
+        acc = {k: 0.0 for k in ("s", "vn", "tau", "vm", "vp")}
+        for t, w in zip(tj, wj):
+            powk = t ** np.arange(N + 1) / fact                              # q(t) = sum_k D_k t^k / k!
+            qm = ein("k,mkqp->mqp", powk, tr[0])
+            qp = ein("k,mkqp->mqp", powk, tr[1])
+            st = fault_state(qm, qp, n, matm, matp, prm, psi)
+            for k in acc:
+                acc[k] = acc[k] + w * st[k]
+            speed = np.sqrt(np.einsum("...i,...i->...", st["V"], st["V"]))
+            psi = psi + w * speed
+            slip = slip + w * st["V"]
+        self.fault_psi[sel] = psi
+        self.fault_slip[sel] = slip
+        self.fault_rate[sel] = st["V"]
+        self.fault_traction[sel] = st["T"]
+        self.fault_normal[sel] = st["S"]
+        # time-integrated middle states, their fluxes at the lattice points,
+        # interpolated to each side's flux points and integrated
+        t_int = acc["s"][..., None] * n + acc["tau"]
+        v_m = acc["vn"][..., None] * n + acc["vm"]
+        v_p = acc["vn"][..., None] * n + acc["vp"]
+        Fm = flux_of_state(*matm, n, v_m, t_int)
+        Fp = flux_of_state(*matp, -n, v_p, -t_int)
+        for e, f, F, L in ((fe, ff, Fm, self.fault_Lm[sel]), (pe, pf, Fp, self.fault_Lp[sel])):
+            scale = 2.0 * self.geo.area[e, f] / self.geo.absdet[e]
+            Fq = np.matmul(L, F)                                             # [m, q, 9]
+            upd = np.zeros((e.size, self.B, 9))
+            for i in range(4):
+                s2 = np.nonzero(f == i)[0]
+                if s2.size:
+                    upd[s2] = scale[s2][:, None, None] * np.matmul((self.phi_f[i] * self.fw[:, None]).T, Fq[s2])
+            out.append((e, upd))
+        return out
+
     def predict(self, elems):
         """Cauchy-Kowalevski time derivatives D^0..D^N of elements -> [n, N+1, B, 9]."""
         D = [self.Q[elems]]
@@ -258,7 +384,7 @@ class Oracle:
                              tuple(m[:, None] * np.ones(nq) for m in matm),
                              (lp[:, None] * np.ones(nq), mp[:, None] * np.ones(nq),
                               rp[:, None] * np.ones(nq)))
-            F[kind == FACE_GRAVITY] = 0.0
+            F[(kind == FACE_GRAVITY) | (kind == FACE_FAULT)] = 0.0
             dQ -= scale[:, None, None] * np.matmul((self.phi_f[i] * self.fw[:, None]).T, F)
             if vel.size:
                 # 2 v_b integrated over the step, 2 (u(t1) - u(t0)), as the neighbour trace
@@ -274,6 +400,10 @@ class Oracle:
                 nv = np.broadcast_to(n[vel][:, None, :], (vel.size, nh, 3))
                 Fh = godunov_flux(np.zeros_like(Pp), Pp, nv, omat, omat)
                 dQ[vel] -= scale[vel][:, None, None] * np.matmul((self.phi_h[i] * self.hw[:, None]).T, Fh)
+
+        # fault faces of this cluster (Sec. 3, friction boundary condition)
+        for e, upd in self._fault_fluxes(c, own, dt):
+            np.subtract.at(dQ, np.searchsorted(elems, e), upd)
 
         # gravity faces of this cluster (Sec. 4.3)
         gsel = np.nonzero(self.cluster[self.grav_elem] == c)[0]

@@ -30,6 +30,7 @@ FACE_ABSORBING = 3
 FACE_WALL = 4
 FACE_FREE = 5
 FACE_VELOCITY = 6
+FACE_FAULT = 7
 
 _KIND = {
     "periodic": FACE_PERIODIC,
@@ -326,6 +327,30 @@ def coupled_box(nx: int, ny: int, nz: int, *, cell: float, water_layers: int,
     z_floor = z_nodes[nz - water_layers]
     rho, lam, mu = layered_materials(m, z_floor)
     m.info.update(z_seafloor=float(z_floor), cell=cell, water_layers=water_layers)
+    return m, (rho, lam, mu)
+
+
+def fault_box(nx: int, ny: int, nz: int, *, cell: float, k_fault: int, jitter: float = 0.0, seed: int = 0,
+              rock=ROCK):
+    """All-rock box with a horizontal dynamic-rupture fault.
+
+    Lateral sides periodic, top and bottom absorbing; the interior faces whose
+    three vertices lie on vertex layer ``k_fault`` (0 < k_fault < nz) are
+    fault faces (kind 7), seen from both sides.
+    The fault is the plane z = z_fault unless ``jitter`` moves its vertices.
+    """
+    if not 0 < k_fault < nz:
+        raise ValueError("the fault must be an interior vertex layer")
+    z_nodes = cell * (np.arange(nz + 1, dtype=np.float64) - k_fault)
+    m = box_mesh(nx, ny, nz, lengths=(nx * cell, ny * cell, 0.0), z_nodes=z_nodes,
+                 sides={"z-": "absorbing", "z+": "absorbing"}, jitter=jitter, seed=seed)
+    k_of = m.tet % (nz + 1)                         # vertex layer of each element vertex
+    for f in range(4):
+        others = [v for v in range(4) if v != f]
+        on = np.all(k_of[:, others] == k_fault, axis=1) & (m.face_kind[:, f] == FACE_INTERIOR)
+        m.face_kind[on, f] = FACE_FAULT
+    rho, lam, mu = uniform_materials(m, rock["rho"], rock["cp"], rock["cs"])
+    m.info.update(cell=cell, k_fault=k_fault, z_fault=0.0)
     return m, (rho, lam, mu)
 
 
