@@ -80,10 +80,12 @@ def fault_state(qm, qp, n, matm, matp, params, psi):
     T = tau0 + lock
     mag = np.sqrt(np.einsum("...i,...i->...", T, T))
     slip = mag > strength
+    # below the strength the point is locked: tau = tau_lock and V = 0 exactly
+    # (|tau| < tau_S in tau_S V = tau |V| leaves only V = 0)
     ratio = np.where(slip, strength / np.where(slip, mag, 1.0), 1.0)
     Tb = ratio[..., None] * T
-    tau = Tb - tau0
-    V = (lock - tau) / eta[..., None]
+    tau = np.where(slip[..., None], Tb - tau0, lock)
+    V = np.where(slip[..., None], (lock - tau) / eta[..., None], 0.0)
     vm = vtm + (tau - ttm) / zsm[..., None]
     vp = vtp - (tau - ttp) / zsp[..., None]
     return dict(s=s, vn=vn, tau=tau, vm=vm, vp=vp, V=V, T=Tb, S=S)
