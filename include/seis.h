@@ -62,8 +62,11 @@ enum {
   SEIS_FACE_ABSORBING = 3, /* zero ghost state */
   SEIS_FACE_WALL = 4,      /* rigid wall: ghost v+ = -v-, same stress */
   SEIS_FACE_FREE = 5,      /* traction-free surface (g = 0): ghost s+ = -s-, same velocity */
-  SEIS_FACE_VELOCITY = 6   /* prescribed velocity v_b = (0, 0, du/dt) of the uplift history set by
+  SEIS_FACE_VELOCITY = 6,  /* prescribed velocity v_b = (0, 0, du/dt) of the uplift history set by
                               seis_set_uplift: ghost v+ = 2 v_b - v-, same stress */
+  SEIS_FACE_FAULT = 7      /* dynamic-rupture fault (Sec. 3, friction boundary condition): an interior
+                              face between two elastic elements, kind 7 on both sides, matched by its
+                              vertex ids; see seis_set_fault. Its two elements share an LTS cluster. */
 };
 
 enum { SEIS_FP64 = 0, SEIS_FP32 = 1, SEIS_BF16 = 2 };
@@ -153,6 +156,7 @@ typedef struct {
   int shape;            /* the predictor's shape: FP32 0 = I~ parked in LDS as far as it fits,
                            1 = in HBM; BF16 0 = 16x16x16 products, 1 = 16x16x32 products */
   int64_t n_acoustic_groups; /* 16-element groups run in the 4-quantity form (options.acoustic) */
+  int64_t n_fault_faces; /* SEIS_FACE_FAULT faces, each counted once (seis_set_fault) */
 } seis_info_t;
 
 /* Default options: FP64, tuned kernels, cfl 0.35, g 9.81, GTS, default stream,
@@ -188,6 +192,32 @@ int seis_write(seis_t *h, const double *dofs, const double *eta);
  * step the ghost contributes the exact time integral 2 (u(t1) - u(t0)).
  * Synchronises the stream; n = 0 removes the forcing. Errors: SEIS_EINVAL. */
 int seis_set_uplift(seis_t *h, int n, const double *src);
+
+/* Friction of the SEIS_FACE_FAULT faces (Sec. 3, fault boundary condition:
+ * |tau| <= tau_S, slip parallel to tau where |tau| = tau_S; linear slip
+ * weakening as in the benchmark of Sec. 6.2). A fault face is listed once,
+ * from its '-' side, the element with the smaller id; n points from '-' to
+ * '+'; faces are ordered by ('-' element, local face); n must equal
+ * seis_info's n_fault_faces. params [n][8], host memory, per face:
+ *   s0       background normal stress (Pa, negative in compression),
+ *   tau0[3]  background traction (Pa; its normal part is ignored),
+ *   mu_s, mu_d, D_c  friction f = mu_s - (mu_s - mu_d) min(psi / D_c, 1) with
+ *            psi the slip path (m), D_c > 0,
+ *   C        cohesion (Pa, >= 0; INFINITY keeps the face locked).
+ * Strength tau_S = C + f max(0, -(s0 + s)) with s the normal stress of the
+ * elements' state; the fault slips where |tau0 + tau| would exceed it.
+ * Until this is called every fault face is locked (a welded interface).
+ * Changes no slip state. Errors: SEIS_EINVAL (n, a parameter out of range). */
+int seis_set_fault(seis_t *h, int64_t n, const double *params);
+
+/* Fault state at the fault's points: out [n_fault_faces][(N+1)(N+2)/2][14]
+ * (host, caller-owned), per point: x, y, z, slip (3, m, v+ - v- integrated
+ * over time), slip path psi (m), slip rate V (3, m/s, at the last time point
+ * of the last step), total shear traction tau0 + tau (3, Pa), total normal
+ * stress s0 + s (Pa). Points are the face's equispaced lattice nodes; match
+ * them by their coordinates. seis_write resets slip, psi and the rates to
+ * zero. Synchronises the stream. */
+int seis_fault_read(seis_t *h, double *out);
 
 /* ADER predictor of every element of cluster c for its next step (Sec. 4.1,
  * Taylor expansion; Cauchy-Kowalevski procedure), its time integral, the

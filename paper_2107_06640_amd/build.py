@@ -20,7 +20,8 @@ LIB = os.path.join(HERE, "libseis.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["refelem.cpp", "setup.cpp", "assemble.hip", "abi.hip", "kernels_plain.hip", "tuned.hip", "tuned_f32.hip",
-           "tuned_bf16.hip", "fno.hip", "energy.hip", "probe.hip", "forcing.hip"]
+           "tuned_bf16.hip", "fno.hip", "energy.hip", "probe.hip", "forcing.hip",
+           "fault.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -13,6 +14,7 @@
 #include "assemble.hpp"
 #include "device.hpp"
 #include "energy.hpp"
+#include "fault.hpp"
 #include "forcing.hpp"
 #include "layout.hpp"
 #include "model.hpp"
@@ -82,6 +84,10 @@ struct seis_t {
   // prescribed-velocity faces: forcing data, the source buffer and the
   // device count of completed macro steps (the forcing's clock)
   ForcingArgs forcing{};
+  // dynamic-rupture faces: friction data, parameters and state on the device
+  FaultArgs fault{};
+  double* fault_par = nullptr;
+  double* fault_state = nullptr;
   double* uplift_src = nullptr;
   int64_t* macro_dev = nullptr;
   // output point sets: seis_points (ids 0, 1, ...), and the sea surface and
@@ -162,14 +168,14 @@ int build_dev(seis_t* h, DevData<T>& d) {
 template <typename T>
 void share_common(const DevData<double>& c, DevData<T>& d) {
   d.tgt = c.tgt; d.mode = c.mode; d.hperm = c.hperm; d.half2 = c.half2; d.rhalf2 = c.rhalf2;
-  d.gslot = c.gslot; d.perm = c.perm; d.Eg = c.Eg; d.Lg = c.Lg; d.g_elem = c.g_elem; d.g_face = c.g_face;
+  d.gslot = c.gslot; d.dslot = c.dslot; d.perm = c.perm; d.Eg = c.Eg; d.Lg = c.Lg; d.g_elem = c.g_elem; d.g_face = c.g_face;
   d.g_par = c.g_par; d.eta = c.eta;
 }
 
 int build_common(seis_t* h, DevData<double>& c) {
   Model& M = h->M;
   Buffers& b = h->buf;
-  int32_t *tgt, *half2, *rhalf2, *gslot, *perm, *gelem;
+  int32_t *tgt, *half2, *rhalf2, *gslot, *dslot, *perm, *gelem;
   int8_t *mode, *hperm, *gface;
   double *Eg, *Lg, *gpar, *eta;
   HIPCHK(h, upload(b, &tgt, M.tgt), "upload tgt");
@@ -178,6 +184,7 @@ int build_common(seis_t* h, DevData<double>& c) {
   HIPCHK(h, upload(b, &half2, M.half2), "upload half2");
   HIPCHK(h, upload(b, &rhalf2, M.rhalf2), "upload rhalf2");
   HIPCHK(h, upload(b, &gslot, M.gslot), "upload gslot");
+  HIPCHK(h, upload(b, &dslot, M.dslot), "upload dslot");
   HIPCHK(h, upload(b, &perm, M.ref.perm), "upload perm");
   HIPCHK(h, upload(b, &Eg, M.ref.Eg), "upload Eg");
   HIPCHK(h, upload(b, &Lg, M.ref.Lg), "upload Lg");
@@ -217,6 +224,40 @@ int build_common(seis_t* h, DevData<double>& c) {
                              1 << (M.C - 1), M.dt_min, 0};
   }
   {
+    // fault faces: geometry, parameters (a locked fault: infinite cohesion) and state
+    const int64_t F = (int64_t)M.f_elem.size();
+    int64_t *fe, *fpe;
+    int8_t *ff, *fpf, *fpm;
+    double *fg, *fE, *tq, *tw;
+    int32_t *pinv;
+    HIPCHK(h, upload(b, &fe, M.f_elem), "upload fault faces");
+    HIPCHK(h, upload(b, &ff, M.f_face), "upload fault faces");
+    HIPCHK(h, upload(b, &fpe, M.f_pelem), "upload fault faces");
+    HIPCHK(h, upload(b, &fpf, M.f_pface), "upload fault faces");
+    HIPCHK(h, upload(b, &fpm, M.f_perm), "upload fault faces");
+    HIPCHK(h, upload(b, &fg, M.f_geo), "upload fault geometry");
+    std::vector<double> par(std::max<int64_t>(F, 1) * kFaultParams, 0.0);
+    for (int64_t k = 0; k < F; ++k) {
+      par[k * kFaultParams + 6] = 1.0;
+      par[k * kFaultParams + 7] = INFINITY;
+    }
+    HIPCHK(h, upload(b, &h->fault_par, par), "upload fault parameters");
+    const int64_t ns = std::max<int64_t>(F, 1) * M.Bf * kFaultState;
+    HIPCHK(h, b.alloc(&h->fault_state, ns), "alloc fault state");
+    HIPCHK(h, hipMemset(h->fault_state, 0, ns * sizeof(double)), "clear fault state");
+    HIPCHK(h, upload(b, &fE, M.ref.E), "upload face traces");
+    HIPCHK(h, upload(b, &pinv, M.ref.pinv), "upload node maps");
+    std::vector<double> gx, gw;
+    gauss_jacobi(M.N + 1, 0.0, 0.0, gx, gw);
+    for (size_t j = 0; j < gx.size(); ++j) {
+      gx[j] = 0.5 * (gx[j] + 1.0);
+      gw[j] *= 0.5;
+    }
+    HIPCHK(h, upload(b, &tq, gx), "upload time points");
+    HIPCHK(h, upload(b, &tw, gw), "upload time weights");
+    h->fault = FaultArgs{fe, ff, fpe, fpf, fpm, fg, h->fault_par, h->fault_state, fE, pinv, dslot, tq, tw};
+  }
+  {
     double *ad, *lmr, *gc, *tw;
     HIPCHK(h, upload(b, &ad, M.a_absdet), "upload absdet");
     HIPCHK(h, upload(b, &lmr, M.a_lmr), "upload materials");
@@ -225,6 +266,7 @@ int build_common(seis_t* h, DevData<double>& c) {
     h->en = EnergyData{M.E, Fg, M.B, M.nq, ad, lmr, gc, tw, eta};
   }
   c.tgt = tgt; c.mode = mode; c.hperm = hperm; c.half2 = half2; c.rhalf2 = rhalf2; c.gslot = gslot;
+  c.dslot = dslot;
   c.perm = perm; c.Eg = Eg; c.Lg = Lg; c.g_elem = gelem; c.g_face = gface; c.g_par = gpar; c.eta = eta;
   c.g = M.g;
   return SEIS_OK;
@@ -357,10 +399,15 @@ int do_predict(seis_t* h, int c0, int c1) {
     }
     return tuned_predict(h->tuned, h->precision, N, c0, c1, e0, e0 + ne, sc, h->stream);
   });
+  // gravity faces, then fault faces (both read the stored time derivatives)
+  const int64_t f0 = M.fault_start[c0], nf = M.fault_start[c1 + 1] - f0;
   if (st == hipSuccess)
-    st = timed(h, 1, ng, [&]() -> hipError_t {
-      if (h->precision == SEIS_FP64) return launch_gravity<double>(N, h->d64, gl, ng, h->stream);
-      return launch_gravity<float>(N, h->d32, gl, ng, h->stream);
+    st = timed(h, 1, ng + nf, [&]() -> hipError_t {
+      hipError_t sg = h->precision == SEIS_FP64 ? launch_gravity<double>(N, h->d64, gl, ng, h->stream)
+                                                : launch_gravity<float>(N, h->d32, gl, ng, h->stream);
+      if (sg != hipSuccess) return sg;
+      if (h->precision == SEIS_FP64) return launch_fault<double>(N, h->fault, h->d64.gD, h->d64.In, f0, nf, h->stream);
+      return launch_fault<float>(N, h->fault, h->d32.gD, h->d32.In, f0, nf, h->stream);
     });
   if (st != hipSuccess) return hip_fail(h, st, "predict launch");
   return SEIS_OK;
@@ -560,11 +607,55 @@ int seis_write(seis_t* h, const double* dofs, const double* eta) {
     HIPCHK(h, hipMemcpy(h->d64.eta, eta, M.g_elem.size() * M.nq * sizeof(double), hipMemcpyHostToDevice),
            "write eta");
   }
-  // a written state starts a new run at time 0 (the clock of the uplift forcing)
+  // a written state starts a new run at time 0 (the clock of the uplift
+  // forcing) with the faults at rest (no slip)
+  if (!M.f_elem.empty())
+    HIPCHK(h, hipMemset(h->fault_state, 0, M.f_elem.size() * M.Bf * kFaultState * sizeof(double)),
+           "clear fault state");
   const int64_t zero = 0;
   HIPCHK(h, hipMemcpy(h->macro_dev, &zero, sizeof(zero), hipMemcpyHostToDevice), "reset macro counter");
   h->macro_done = 0;
   reset_cursor(h);
+  return SEIS_OK;
+}
+
+int seis_set_fault(seis_t* h, int64_t n, const double* params) {
+  if (!h) return SEIS_EINVAL;
+  const Model& M = h->M;
+  const int64_t F = (int64_t)M.f_elem.size();
+  if (n != F || (F > 0 && !params)) return fail(h, SEIS_EINVAL, "seis_set_fault: n must equal the number of fault faces");
+  std::vector<double> par(std::max<int64_t>(F, 1) * kFaultParams, 0.0);
+  for (int64_t k = 0; k < F; ++k) {
+    const double* p = params + k * kFaultParams;
+    if (!(p[4] >= 0.0) || !(p[5] >= 0.0) || !(p[6] > 0.0) || !(p[7] >= 0.0))
+      return fail(h, SEIS_EINVAL, "seis_set_fault: need mu_s, mu_d >= 0, D_c > 0, C >= 0");
+    for (int i = 0; i < kFaultParams; ++i) par[M.fault_abi[k] * kFaultParams + i] = p[i];
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  if (F > 0)
+    HIPCHK(h, hipMemcpy(h->fault_par, par.data(), F * kFaultParams * sizeof(double), hipMemcpyHostToDevice),
+           "write fault parameters");
+  return SEIS_OK;
+}
+
+int seis_fault_read(seis_t* h, double* out) {
+  if (!h) return SEIS_EINVAL;
+  const Model& M = h->M;
+  const int64_t F = (int64_t)M.f_elem.size();
+  if (F == 0) return SEIS_OK;
+  if (!out) return SEIS_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  std::vector<double> st(F * M.Bf * kFaultState);
+  HIPCHK(h, hipMemcpy(st.data(), h->fault_state, st.size() * sizeof(double), hipMemcpyDeviceToHost),
+         "read fault state");
+  for (int64_t k = 0; k < F; ++k) {
+    const int64_t f = M.fault_abi[k];
+    for (int m = 0; m < M.Bf; ++m) {
+      double* o = out + (k * M.Bf + m) * (3 + kFaultState);
+      for (int d = 0; d < 3; ++d) o[d] = M.f_xyz[(f * M.Bf + m) * 3 + d];
+      for (int i = 0; i < kFaultState; ++i) o[3 + i] = st[(f * M.Bf + m) * kFaultState + i];
+    }
+  }
   return SEIS_OK;
 }
 
@@ -826,6 +917,7 @@ int seis_info(const seis_t* h, seis_info_t* info) {
   info->fused = h->fused ? 1 : 0;
   info->shape = h->tuned.pc.variant;
   info->n_acoustic_groups = h->tuned.n_acoustic_groups;
+  info->n_fault_faces = (int64_t)M.f_elem.size();
   return SEIS_OK;
 }
 

@@ -62,6 +62,16 @@ __global__ __launch_bounds__(64) void k_assemble(AsmInput in, AsmOutput<T> out) 
     T* fp = out.Fp + id * 81;
     if (kind == 2) {  // gravity face: the eta ODE supplies the whole flux
       for (int i = 0; i < 81; ++i) fm[i] = fp[i] = (T)0;
+    } else if (kind == 7) {
+      // fault face: the friction kernel supplies the middle state w^b in the
+      // inbox; the flux is T A T^-1 w^b (A reads only the components of w^b
+      // that the middle state sets)
+      mul9(Tr, A, Y);
+      mul9(Y, Ti, X);
+      for (int i = 0; i < 81; ++i) {
+        fm[i] = (T)0;
+        fp[i] = (T)(scale * X[i]);
+      }
     } else {
       mul9(A, Gm, X);
       mul9(Tr, X, Y);

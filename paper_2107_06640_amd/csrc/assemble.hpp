@@ -144,11 +144,17 @@ __host__ __device__ inline void middle_state(double zpm, double zsm, double zpp,
 //   t_t^b = c4 t_t + c5 v_t,  v_t^b = c6 t_t + c7 v_t
 // summed over the own trace (cm) and the neighbour trace (cp); the flux is
 // then A-hat^-(n) applied to (v^b, traction s_n^b n + t_t^b). Ghost states of
-// physical boundaries (Sec. 4.3) are folded into cm.
+// physical boundaries (Sec. 4.3) are folded into cm. A fault face (kind 7)
+// receives its middle state itself (the friction kernel writes it where the
+// neighbour trace would be): cm = 0 and cp the identity.
 __host__ __device__ inline void pointwise_coeffs(int kind, double zpm, double zsm, double zpp, double zsp,
                                                  double s, double cm[8], double cp[8]) {
   for (int i = 0; i < 8; ++i) cm[i] = cp[i] = 0.0;
   if (kind == 2) return;  // gravity surface: handled by the eta ODE
+  if (kind == 7) {
+    cp[0] = cp[3] = cp[4] = cp[7] = s;
+    return;
+  }
   const double c1 = zpm * zpp / (zpm + zpp);
   double a[8], b[8];
   a[0] = 1.0 - c1 / zpp; a[1] = -c1; b[0] = c1 / zpp; b[1] = c1;

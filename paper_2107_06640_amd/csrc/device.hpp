@@ -52,6 +52,7 @@ struct DevData {
   const int32_t* half2;
   const int32_t* rhalf2;
   const int32_t* gslot;
+  const int32_t* dslot;  // [E] slot of the stored time derivatives (gravity faces, fault faces, ...), -1 none
   T* gD;
   // reference matrices (compute type)
   const T* K;   // [3][B][B]

@@ -1,0 +1,153 @@
+// Friction kernel of the dynamic-rupture faces (see fault.hpp).
+#include "fault.hpp"
+
+#include "elastic.hpp"
+#include "layout.hpp"
+
+namespace seis {
+
+namespace {
+
+// traction s n split into its normal and tangential parts, and the same for v
+__device__ inline void split_state(const double* q, const double* n, double& sn, double* tt, double& vn,
+                                   double* vt) {
+  const double tx = q[0] * n[0] + q[3] * n[1] + q[5] * n[2];
+  const double ty = q[3] * n[0] + q[1] * n[1] + q[4] * n[2];
+  const double tz = q[5] * n[0] + q[4] * n[1] + q[2] * n[2];
+  sn = tx * n[0] + ty * n[1] + tz * n[2];
+  tt[0] = tx - sn * n[0];
+  tt[1] = ty - sn * n[1];
+  tt[2] = tz - sn * n[2];
+  vn = q[6] * n[0] + q[7] * n[1] + q[8] * n[2];
+  for (int d = 0; d < 3; ++d) vt[d] = q[6 + d] - vn * n[d];
+}
+
+// one work-group per fault face; thread m handles face node m
+template <typename T, int N>
+__global__ __launch_bounds__(64) void k_fault(FaultArgs a, const T* gD, T* In, int64_t f0) {
+  constexpr int B = nbasis(N), Bf = nface(N), FT = row_tiles(Bf);
+  __shared__ double tr[2][N + 1][Bf][9];  // traces of the time derivatives at the nodes
+  const int64_t f = f0 + blockIdx.x;
+  const int64_t em = a.elem[f], ep = a.pelem[f];
+  const int fm = a.face[f], fp = a.pface[f], h = a.perm[f];
+  const T* Dm = gD + (int64_t)a.dslot[em] * (N + 1) * B * 9;
+  const T* Dp = gD + (int64_t)a.dslot[ep] * (N + 1) * B * 9;
+  for (int i = threadIdx.x; i < 2 * (N + 1) * Bf * 9; i += blockDim.x) {
+    const int side = i / ((N + 1) * Bf * 9), r = i % ((N + 1) * Bf * 9);
+    const int k = r / (Bf * 9), m = (r / 9) % Bf, p = r % 9;
+    const int node = side == 0 ? m : a.pinv[h * Bf + m];
+    const double* Em = a.E + ((int64_t)(side == 0 ? fm : fp) * Bf + node) * B;
+    const T* D = (side == 0 ? Dm : Dp) + (int64_t)k * B * 9 + p;
+    double acc = 0.0;
+    for (int l = 0; l < B; ++l) acc += Em[l] * (double)D[l * 9];
+    tr[side][k][m][p] = acc;
+  }
+  __syncthreads();
+  const int m = threadIdx.x;
+  if (m >= Bf) return;
+  const double* g = a.geo + f * 8;
+  const double n[3] = {g[0], g[1], g[2]};
+  const double zpm = g[3], zsm = g[4], zpp = g[5], zsp = g[6], dt = g[7];
+  const double* pr = a.par + f * kFaultParams;
+  const double s0 = pr[0];
+  const double t0n = pr[1] * n[0] + pr[2] * n[1] + pr[3] * n[2];
+  const double tau0[3] = {pr[1] - t0n * n[0], pr[2] - t0n * n[1], pr[3] - t0n * n[2]};
+  const double mu_s = pr[4], mu_d = pr[5], dc = pr[6], coh = pr[7];
+  const double eta = zsm * zsp / (zsm + zsp);
+  double* st = a.state + (f * Bf + m) * kFaultState;
+  double slip[3] = {st[0], st[1], st[2]}, psi = st[3];
+  double V[3] = {0.0, 0.0, 0.0}, Tb[3] = {0.0, 0.0, 0.0}, Stot = 0.0;
+  double as = 0.0, avn = 0.0, atau[3] = {0.0, 0.0, 0.0}, avm[3] = {0.0, 0.0, 0.0}, avp[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j <= N; ++j) {
+    const double tj = a.tq[j], wj = a.tw[j];
+    double qm[9], qp[9];
+    for (int p = 0; p < 9; ++p) {
+      double x = 0.0, y = 0.0, pw = 1.0;
+      for (int k = 0; k <= N; ++k) {  // q(t) = sum_k D~k (t / dt)^k
+        x += pw * tr[0][k][m][p];
+        y += pw * tr[1][k][m][p];
+        pw *= tj;
+      }
+      qm[p] = x;
+      qp[p] = y;
+    }
+    double snm, ttm[3], vnm, vtm[3], snp, ttp[3], vnp, vtp[3];
+    split_state(qm, n, snm, ttm, vnm, vtm);
+    split_state(qp, n, snp, ttp, vnp, vtp);
+    const double s = (zpp * snm + zpm * snp + zpm * zpp * (vnp - vnm)) / (zpm + zpp);
+    const double vn = (zpm * vnm + zpp * vnp + snp - snm) / (zpm + zpp);
+    double lock[3], Ttot[3];
+    for (int d = 0; d < 3; ++d) {
+      lock[d] = eta * (ttm[d] / zsm + ttp[d] / zsp + vtp[d] - vtm[d]);
+      Ttot[d] = tau0[d] + lock[d];
+    }
+    Stot = s0 + s;
+    const double fr = mu_s - (mu_s - mu_d) * fmin(psi / dc, 1.0);
+    const double strength = coh + fr * fmax(0.0, -Stot);
+    const double mag = sqrt(Ttot[0] * Ttot[0] + Ttot[1] * Ttot[1] + Ttot[2] * Ttot[2]);
+    // below the strength the point is locked: tau = tau_lock, V = 0 exactly
+    const bool slips = mag > strength;
+    const double ratio = slips ? strength / mag : 1.0;
+    double speed2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      Tb[d] = ratio * Ttot[d];
+      const double tau = slips ? Tb[d] - tau0[d] : lock[d];
+      V[d] = slips ? (lock[d] - tau) / eta : 0.0;
+      speed2 += V[d] * V[d];
+      atau[d] += wj * tau;
+      avm[d] += wj * (vtm[d] + (tau - ttm[d]) / zsm);
+      avp[d] += wj * (vtp[d] - (tau - ttp[d]) / zsp);
+      slip[d] += wj * dt * V[d];
+    }
+    as += wj * s;
+    avn += wj * vn;
+    psi += wj * dt * sqrt(speed2);
+  }
+  for (int d = 0; d < 3; ++d) {
+    st[d] = slip[d];
+    st[4 + d] = V[d];
+    st[7 + d] = Tb[d];
+  }
+  st[3] = psi;
+  st[10] = Stot;
+  // time-averaged middle states: stress s n n + tau n + n tau, velocity vn n + v_t
+  double sig[6];
+  sig[0] = as * n[0] * n[0] + 2.0 * atau[0] * n[0];
+  sig[1] = as * n[1] * n[1] + 2.0 * atau[1] * n[1];
+  sig[2] = as * n[2] * n[2] + 2.0 * atau[2] * n[2];
+  sig[3] = as * n[0] * n[1] + atau[0] * n[1] + atau[1] * n[0];
+  sig[4] = as * n[1] * n[2] + atau[1] * n[2] + atau[2] * n[1];
+  sig[5] = as * n[0] * n[2] + atau[0] * n[2] + atau[2] * n[0];
+  const int mr = a.pinv[h * Bf + m];
+  for (int p = 0; p < 6; ++p) {
+    In[inidx(em, fm, m, p, FT)] = (T)sig[p];
+    In[inidx(ep, fp, mr, p, FT)] = (T)sig[p];
+  }
+  for (int d = 0; d < 3; ++d) {
+    In[inidx(em, fm, m, 6 + d, FT)] = (T)(avn * n[d] + avm[d]);
+    In[inidx(ep, fp, mr, 6 + d, FT)] = (T)(avn * n[d] + avp[d]);
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fault(int N, const FaultArgs& a, const T* gD, T* In, int64_t f0, int64_t nf, hipStream_t s) {
+  if (nf <= 0) return hipSuccess;
+  if (!a.elem || !a.face || !a.pelem || !a.pface || !a.perm || !a.geo || !a.par || !a.state || !a.E || !a.pinv ||
+      !a.dslot || !a.tq || !a.tw || !gD || !In)
+    return hipErrorInvalidValue;
+  switch (N) {
+#define SEIS_F(NN) \
+  case NN: hipLaunchKernelGGL((k_fault<T, NN>), dim3((unsigned)nf), dim3(64), 0, s, a, gD, In, f0); break;
+    SEIS_F(2) SEIS_F(3) SEIS_F(4) SEIS_F(5) SEIS_F(6)
+#undef SEIS_F
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_fault<double>(int, const FaultArgs&, const double*, double*, int64_t, int64_t, hipStream_t);
+template hipError_t launch_fault<float>(int, const FaultArgs&, const float*, float*, int64_t, int64_t, hipStream_t);
+
+}  // namespace seis

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(NT_TALL) void k_predict_plain(DevData<T> d, int64_t
   __shared__ T sG[9], sM[3];
   if (tid < 9) sG[tid] = d.G[e * 9 + tid];
   if (tid < 3) sM[tid] = d.mat[e * 3 + tid];
-  const int gs = d.gslot[e];
+  const int gs = d.dslot[e];
   T* gD = gs >= 0 ? d.gD + (int64_t)gs * (N + 1) * B * 9 : nullptr;
   for (int i = tid; i < B * 9; i += NT) {
     const T q = d.Q[qidx(e, i / 9, i % 9, RT)];

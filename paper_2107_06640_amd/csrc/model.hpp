@@ -82,6 +82,17 @@ struct Model {
   std::vector<int64_t> floor_elem;
   std::vector<int8_t> floor_face;
 
+  // dynamic-rupture fault faces (kind 7), seen from their '-' side (the
+  // element with the smaller caller id), grouped by cluster
+  // ([fault_start[c], fault_start[c+1])); element ids in library order
+  std::vector<int64_t> f_elem, f_pelem;  // '-' and '+' elements
+  std::vector<int8_t> f_face, f_pface;   // their local faces
+  std::vector<int8_t> f_perm;            // node map: '-' node m is '+' node perm[f_perm][m]
+  std::vector<double> f_geo;             // [F][8]: n (from - to +), Zp-, Zs-, Zp+, Zs+, dt
+  std::vector<double> f_xyz;             // [F][Bf][3] face nodes ('-' numbering)
+  std::vector<int64_t> fault_start;      // [C+1]
+  std::vector<int64_t> fault_abi;        // [F]: library position of the ABI's fault face k
+
   RefElement ref;
 };
 

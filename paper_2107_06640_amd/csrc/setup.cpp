@@ -48,7 +48,7 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
         return err.str();
       }
     for (int f = 0; f < 4; ++f)
-      if (face_kind[e * 4 + f] < 0 || face_kind[e * 4 + f] > 6) {
+      if (face_kind[e * 4 + f] < 0 || face_kind[e * 4 + f] > 7) {
         err << "element " << e << ": bad face kind";
         return err.str();
       }
@@ -131,7 +131,7 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
     keys.reserve(E * 4);
     for (int64_t e = 0; e < E; ++e)
       for (int f = 0; f < 4; ++f)
-        if (face_kind[e * 4 + f] == 0) {
+        if (face_kind[e * 4 + f] == 0 || face_kind[e * 4 + f] == 7) {
           FaceKey k;
           for (int a = 0; a < 3; ++a) k.k[a] = tet[e * 4 + FACE_V[f][a]];
           std::sort(k.k, k.k + 3);
@@ -145,6 +145,11 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
           !(i + 2 < keys.size() && key_eq(keys[i], keys[i + 2]))) {
         nb[keys[i].id] = keys[i + 1].id;
         nb[keys[i + 1].id] = keys[i].id;
+        if (face_kind[keys[i].id] != face_kind[keys[i + 1].id]) {
+          err << "fault face of element " << keys[i].id / 4 << " (face " << keys[i].id % 4
+              << ") meets a face that is not a fault face";
+          return err.str();
+        }
         i += 2;
       } else {
         err << "interior face of element " << keys[i].id / 4 << " (face " << keys[i].id % 4
@@ -201,7 +206,7 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
       for (int b = 0; b < 3; ++b) {
         const int64_t vb = tet[e2 * 4 + FACE_V[f2][b]];
         bool same;
-        if (face_kind[id] == 0) {
+        if (face_kind[id] == 0 || face_kind[id] == 7) {
           same = (va == vb);
         } else {
           double d2 = 0.0;
@@ -243,6 +248,13 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
     }
   }
 
+  // ---- fault faces: elastic on both sides
+  for (int64_t id = 0; id < E * 4; ++id)
+    if (face_kind[id] == 7 && !(mu[id / 4] > 0.0)) {
+      err << "fault face on acoustic element " << id / 4;
+      return err.str();
+    }
+
   // ---- time steps and rate-2 clusters (Sec. 4.4)
   std::vector<double> dtk(E);
   double dmin = 1e300;
@@ -257,13 +269,16 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
     c = std::max(0, std::min(c, max_clusters - 1));
     cl[e] = c;
   }
+  // neighbours differ by at most one cluster; the two sides of a fault face
+  // share one (the friction law couples them pointwise in time)
   for (bool changed = true; changed;) {
     changed = false;
     for (int64_t id = 0; id < E * 4; ++id) {
       if (nb[id] < 0) continue;
       const int64_t e = id / 4, e2 = nb[id] / 4;
-      if (cl[e] > cl[e2] + 1) {
-        cl[e] = cl[e2] + 1;
+      const int up = face_kind[id] == 7 ? 0 : 1;
+      if (cl[e] > cl[e2] + up) {
+        cl[e] = cl[e2] + up;
         changed = true;
       }
     }
@@ -337,9 +352,10 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
       if (nb[id] < 0) continue;
       const int64_t e2 = nb[id] / 4, f2 = nb[id] % 4;
       const int64_t k2 = M.new_of_old[e2];
-      M.tgt[kn * 4 + f] = int32_t(k2 * 4 + f2);
       // node map for the receiving face: its vertex a == my vertex sigma'[a]
       M.hperm[kn * 4 + f] = hmap[nb[id]];
+      if (face_kind[id] == 7) continue;  // fault: the friction kernel fills both inboxes
+      M.tgt[kn * 4 + f] = int32_t(k2 * 4 + f2);
       const int dc = cl[e2] - cl[e];
       if (dc == 0) M.mode[kn * 4 + f] = MODE_SAME;
       else if (dc == -1) {
@@ -403,6 +419,46 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
     }
   }
   M.vface_start[C] = (int64_t)M.v_elem.size();
+  // ---- fault faces from their '-' side (the smaller caller element id),
+  // grouped by cluster (ABI order = by caller (element, face) of that side)
+  {
+    std::vector<std::pair<int64_t, int>> fl;  // caller (element, face)
+    for (int64_t e = 0; e < E; ++e)
+      for (int f = 0; f < 4; ++f)
+        if (face_kind[e * 4 + f] == 7 && nb[e * 4 + f] / 4 > e) fl.push_back({e, f});
+    M.fault_start.assign(C + 1, 0);
+    std::vector<std::vector<int64_t>> by_c(C);
+    for (int64_t k = 0; k < (int64_t)fl.size(); ++k) by_c[cl[fl[k].first]].push_back(k);
+    M.fault_abi.assign(fl.size(), 0);
+    for (int c = 0; c < C; ++c) {
+      M.fault_start[c] = (int64_t)M.f_elem.size();
+      for (int64_t k : by_c[c]) {
+        const int64_t e = fl[k].first, id = e * 4 + fl[k].second;
+        const int64_t e2 = nb[id] / 4;
+        M.fault_abi[k] = (int64_t)M.f_elem.size();
+        M.f_elem.push_back(M.new_of_old[e]);
+        M.f_face.push_back(int8_t(fl[k].second));
+        M.f_pelem.push_back(M.new_of_old[e2]);
+        M.f_pface.push_back(int8_t(nb[id] % 4));
+        M.f_perm.push_back(hmap[nb[id]]);
+        const double zpm = std::sqrt((lam[e] + 2 * mu[e]) * rho[e]), zsm = std::sqrt(mu[e] * rho[e]);
+        const double zpp = std::sqrt((lam[e2] + 2 * mu[e2]) * rho[e2]), zsp = std::sqrt(mu[e2] * rho[e2]);
+        const double geo[8] = {normal[id * 3], normal[id * 3 + 1], normal[id * 3 + 2], zpm, zsm, zpp, zsp,
+                               M.dt_c[cl[e]]};
+        for (int p = 0; p < 8; ++p) M.f_geo.push_back(geo[p]);
+        const double* X[4];
+        for (int v = 0; v < 4; ++v) X[v] = xyz + 3 * tet[e * 4 + v];
+        for (int m = 0; m < R.Bf; ++m) {
+          double xi[3];
+          face_to_ref(fl[k].second, R.node_st[2 * m], R.node_st[2 * m + 1], xi);
+          for (int d = 0; d < 3; ++d)
+            M.f_xyz.push_back(X[0][d] + (X[1][d] - X[0][d]) * xi[0] + (X[2][d] - X[0][d]) * xi[1] +
+                              (X[3][d] - X[0][d]) * xi[2]);
+        }
+      }
+    }
+    M.fault_start[C] = (int64_t)M.f_elem.size();
+  }
   M.xyz.assign(xyz, xyz + nv * 3);
   M.tet.assign(tet, tet + E * 4);
   M.g_order.resize(M.g_elem.size());
@@ -412,12 +468,16 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
   M.dslot.assign(E, -1);
   int64_t nd = (int64_t)M.g_elem.size();
   for (int64_t k = 0; k < E; ++k) M.dslot[k] = M.gslot[k];
+  std::vector<char> on_fault(E, 0);
+  for (size_t k = 0; k < M.f_elem.size(); ++k) on_fault[M.f_elem[k]] = on_fault[M.f_pelem[k]] = 1;
   for (int64_t k = 0; k < E; ++k) {
     bool finer = false;
     for (int f = 0; f < 4; ++f) finer = finer || M.mode[k * 4 + f] == MODE_FINER;
-    if (finer && M.dslot[k] < 0) M.dslot[k] = int32_t(nd++);
+    if ((finer || on_fault[k]) && M.dslot[k] < 0) M.dslot[k] = int32_t(nd++);
   }
   M.n_dslot = nd;
+  for (size_t k = 0; k < M.f_elem.size(); ++k)
+    if (M.dslot[M.f_elem[k]] < 0 || M.dslot[M.f_pelem[k]] < 0) return "fault element without a derivative slot";
   M.fix_start.assign(C + 1, 0);
   M.h2_start.assign(C + 1, 0);
   for (int c = 0; c < C; ++c) {

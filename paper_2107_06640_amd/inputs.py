@@ -331,17 +331,21 @@ def coupled_box(nx: int, ny: int, nz: int, *, cell: float, water_layers: int,
 
 
 def fault_box(nx: int, ny: int, nz: int, *, cell: float, k_fault: int, jitter: float = 0.0, seed: int = 0,
-              rock=ROCK):
+              rock=ROCK, z_nodes=None):
     """All-rock box with a horizontal dynamic-rupture fault.
 
     Lateral sides periodic, top and bottom absorbing; the interior faces whose
     three vertices lie on vertex layer ``k_fault`` (0 < k_fault < nz) are
-    fault faces (kind 7), seen from both sides.
-    The fault is the plane z = z_fault unless ``jitter`` moves its vertices.
+    fault faces (kind 7), seen from both sides. ``z_nodes`` (default: layers
+    of thickness ``cell`` with the fault at z = 0) sets the vertex layers.
+    The fault is the plane z = z_nodes[k_fault] unless ``jitter`` moves its
+    vertices.
     """
     if not 0 < k_fault < nz:
         raise ValueError("the fault must be an interior vertex layer")
-    z_nodes = cell * (np.arange(nz + 1, dtype=np.float64) - k_fault)
+    if z_nodes is None:
+        z_nodes = cell * (np.arange(nz + 1, dtype=np.float64) - k_fault)
+    z_nodes = np.asarray(z_nodes, dtype=np.float64)
     m = box_mesh(nx, ny, nz, lengths=(nx * cell, ny * cell, 0.0), z_nodes=z_nodes,
                  sides={"z-": "absorbing", "z+": "absorbing"}, jitter=jitter, seed=seed)
     k_of = m.tet % (nz + 1)                         # vertex layer of each element vertex
@@ -350,7 +354,7 @@ def fault_box(nx: int, ny: int, nz: int, *, cell: float, k_fault: int, jitter: f
         on = np.all(k_of[:, others] == k_fault, axis=1) & (m.face_kind[:, f] == FACE_INTERIOR)
         m.face_kind[on, f] = FACE_FAULT
     rho, lam, mu = uniform_materials(m, rock["rho"], rock["cp"], rock["cs"])
-    m.info.update(cell=cell, k_fault=k_fault, z_fault=0.0)
+    m.info.update(cell=cell, k_fault=k_fault, z_fault=float(z_nodes[k_fault]))
     return m, (rho, lam, mu)
 
 

@@ -23,7 +23,9 @@ ERRORS = {-1: "SEIS_EINVAL", -2: "SEIS_ENOMEM", -3: "SEIS_EDEVICE", -4: "SEIS_EO
 EXPORTED = ["seis_default_options", "seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step",
             "seis_run", "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
             "seis_destroy", "seis_last_error", "seis_profile", "seis_profile_read", "seis_energy",
-            "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample", "seis_set_uplift"]
+            "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample", "seis_set_uplift",
+            "seis_set_fault", "seis_fault_read"]
+FAULT_POINT_VALUES = 14  # x, y, z, slip (3), slip path, slip rate (3), shear traction (3), normal stress
 SEIS_POINTS_SEA_SURFACE, SEIS_POINTS_SEAFLOOR = -1, -2
 
 
@@ -55,7 +57,8 @@ class Info_t(C.Structure):
                 ("n_elements", C.c_int64), ("n_gravity_faces", C.c_int64), ("dt_min", C.c_double),
                 ("time", C.c_double), ("cluster_size", C.c_int64 * 16), ("updates_per_macro_step", C.c_int64),
                 ("device_bytes", C.c_int64), ("launch", C.c_int * 8), ("launch_source", C.c_int),
-                ("fused", C.c_int), ("shape", C.c_int), ("n_acoustic_groups", C.c_int64)]
+                ("fused", C.c_int), ("shape", C.c_int), ("n_acoustic_groups", C.c_int64),
+                ("n_fault_faces", C.c_int64)]
 
 
 _lib = None
@@ -101,6 +104,8 @@ def load_library(path: str = LIB_PATH):
     lib.seis_points_info.argtypes = [P, C.c_int, C.POINTER(C.c_int64), dp, C.POINTER(C.c_int64)]
     lib.seis_sample.argtypes = [P, C.c_int, C.c_void_p, C.c_void_p]
     lib.seis_set_uplift.argtypes = [P, C.c_int, dp]
+    lib.seis_set_fault.argtypes = [P, C.c_int64, dp]
+    lib.seis_fault_read.argtypes = [P, dp]
     lib.seis_energy_noalloc.argtypes = [P, C.c_void_p]
     lib.seis_destroy.argtypes = [P]
     lib.seis_destroy.restype = None
@@ -108,7 +113,8 @@ def load_library(path: str = LIB_PATH):
     lib.seis_last_error.restype = C.c_char_p
     for name in ("seis_setup", "seis_write", "seis_predict", "seis_correct", "seis_step", "seis_run",
                  "seis_read", "seis_read_elements", "seis_info", "seis_cluster_of", "seis_sync",
-                 "seis_profile", "seis_profile_read", "seis_energy", "seis_energy_noalloc", "seis_points", "seis_points_info", "seis_sample", "seis_set_uplift"):
+                 "seis_profile", "seis_profile_read", "seis_energy", "seis_energy_noalloc", "seis_points",
+                 "seis_points_info", "seis_sample", "seis_set_uplift", "seis_set_fault", "seis_fault_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -192,6 +198,20 @@ class Solver:
         """Uplift history of the prescribed-velocity faces: sources [n][5] = (A, x, y, w, T)."""
         src = np.ascontiguousarray(sources, dtype=np.float64).reshape(-1, 5)
         self._check(self._lib.seis_set_uplift(self._h, src.shape[0], _ptr(src, C.c_double)))
+
+    def set_fault(self, params):
+        """Friction of the fault faces: params [n_fault_faces][8] (or one row for all) =
+        (s0, tau0_x, tau0_y, tau0_z, mu_s, mu_d, D_c, C)."""
+        n = self.info()["n_fault_faces"]
+        p = np.ascontiguousarray(np.broadcast_to(np.asarray(params, dtype=np.float64), (n, 8)))
+        self._check(self._lib.seis_set_fault(self._h, n, _ptr(p, C.c_double)))
+
+    def fault_read(self):
+        """Fault state [n_fault_faces][n_face_nodes][14] (see FAULT_POINT_VALUES)."""
+        inf = self.info()
+        out = np.zeros((inf["n_fault_faces"], inf["n_face_nodes"], FAULT_POINT_VALUES))
+        self._check(self._lib.seis_fault_read(self._h, _ptr(out, C.c_double)))
+        return out
 
     def predict(self, c):
         self._check(self._lib.seis_predict(self._h, int(c)))
