@@ -116,11 +116,27 @@ WORKLOADS = {
     # the same box with +-10% jitter: three clusters that each carry a real
     # share of the updates (LTS saves a third of them)
     "cfg3-lts": 0.1,
+    # rock box of 64 x 64 x 32 cubes (786 432 tets, 500 m cells, +-10%
+    # jitter) with a dynamic-rupture fault at mid-depth: 8192 fault faces
+    # under a background traction above the static strength (the whole
+    # fault slips), and the same mesh welded (fault faces interior)
+    "fault": 0.1,
+    "fault-welded": 0.1,
 }
+
+# friction of the fault workload: s0 = -50 MPa, tau0 = 31 MPa along x,
+# mu_s 0.6, mu_d 0.5, D_c 0.4 m, no cohesion
+FAULT_PARAMS = [-50e6, 31e6, 0.0, 0.0, 0.6, 0.5, 0.4, 0.0]
 
 
 def workload(scale, seed=0, name="cfg3"):
     from paper_2107_06640_amd import inputs
+    if name.startswith("fault"):
+        n = 64 // scale
+        mesh, mats = inputs.fault_box(n, n, n // 2, cell=500.0, k_fault=n // 4, jitter=WORKLOADS[name], seed=seed)
+        if name == "fault-welded":
+            mesh.face_kind[mesh.face_kind == inputs.FACE_FAULT] = inputs.FACE_INTERIOR
+        return mesh, mats
     mesh, mats = inputs.cfg3(scale=scale, seed=seed, jitter=WORKLOADS[name])
     return mesh, mats
 
@@ -321,10 +337,7 @@ def main():
         "vs_baseline": None,
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: graded jittered ocean-over-solid box "
-                               f"(jitter {WORKLOADS[args.workload]}), {inf['n_elements']} tets, "
-                               f"order {args.order} (B={inf['n_basis']}), rate-2 LTS {inf['n_clusters']} clusters "
-                               f"{inf['cluster_size']}, {inf['n_gravity_faces']} gravity faces",
+        "config": {"workload": workload_description(args, inf),
                    "kernel": args.kernel, "precision": args.precision, "elements": inf["n_elements"],
                    "graph": bool(args.graph), "fused": bool(inf["fused"]),
                    "eager_ms_per_step": eager_ms / args.steps,
@@ -356,6 +369,17 @@ def main():
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}
 
 
+def workload_description(args, inf):
+    if args.workload.startswith("fault"):
+        what = (f"rock box with a mid-depth dynamic-rupture fault, {inf['n_fault_faces']} fault faces slipping"
+                if args.workload == "fault" else "rock box, the fault plane welded (interior faces)")
+    else:
+        what = "graded jittered ocean-over-solid box"
+    return (f"{args.workload}: {what} (jitter {WORKLOADS[args.workload]}), {inf['n_elements']} tets, "
+            f"order {args.order} (B={inf['n_basis']}), rate-2 LTS {inf['n_clusters']} clusters "
+            f"{inf['cluster_size']}, {inf['n_gravity_faces']} gravity faces")
+
+
 def measure(args, mesh, mats, precision, stream):
     """Set up the solver, warm up, and time args.steps macro steps on the library's stream.
 
@@ -373,6 +397,8 @@ def measure(args, mesh, mats, precision, stream):
                        acoustic=not args.nine_quantity_water)
     try:
         inf = s.info()
+        if inf["n_fault_faces"]:
+            s.set_fault(FAULT_PARAMS)
         q = tiled_dofs(mesh.n_elements, inf["n_basis"], 0, mats[2] == 0)
         s.write(q)
         del q

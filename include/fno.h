@@ -49,7 +49,9 @@ int fno_bias_act(int64_t n_outer, int64_t C, int64_t S, float *z, const float *b
 /* dz = da * gelu'(z) elementwise over n values (dz may equal da). */
 int fno_gelu_backward(int64_t n, const float *z, const float *da, float *dz, void *stream);
 
-/* db[c] = sum over o < n_outer, s < S of dz[o][c][s] (overwrites db). */
+/* db[c] = sum over o < n_outer, s < S of dz[o][c][s] (overwrites db; partial
+ * sums of work-groups are added atomically, so the summation order, and the
+ * last bits, may vary from call to call). C <= 65535. */
 int fno_channel_sum(int64_t n_outer, int64_t C, int64_t S, const float *dz, float *db, void *stream);
 
 /* Adam step t >= 1 on n parameters: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;

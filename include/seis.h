@@ -268,9 +268,9 @@ int seis_cluster_of(const seis_t *h, int32_t *out);
 int seis_profile(seis_t *h, int enable);
 
 /* Totals since profiling was enabled, for the kernel kinds
- * [0] predictor, [1] gravity face, [2] corrector: elapsed ms, number of
- * launches and number of elements (gravity: faces) processed. Any pointer may
- * be NULL. Synchronises the stream. */
+ * [0] predictor, [1] gravity face, [2] corrector, [3] fault face (arrays of
+ * 4): elapsed ms, number of launches and number of elements (gravity and
+ * fault: faces) processed. Any pointer may be NULL. Synchronises the stream. */
 int seis_profile_read(seis_t *h, double *ms, int64_t *launches, int64_t *elements);
 
 /* Output at points (Sec. 6.2 writes receivers every 0.01 s, and the sea

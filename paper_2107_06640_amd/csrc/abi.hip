@@ -75,8 +75,8 @@ struct seis_t {
   size_t used = 0;
   struct Rec { int kind; hipEvent_t a, b; int64_t n; };
   std::vector<Rec> recs;
-  double tot_ms[3] = {0, 0, 0};
-  int64_t tot_launch[3] = {0, 0, 0}, tot_elem[3] = {0, 0, 0};
+  double tot_ms[4] = {0, 0, 0, 0};
+  int64_t tot_launch[4] = {0, 0, 0, 0}, tot_elem[4] = {0, 0, 0, 0};
   // energy and field norms: FP64 weights, and the partial sums of seis_energy
   // (allocated at its first call)
   EnergyData en{};
@@ -400,12 +400,14 @@ int do_predict(seis_t* h, int c0, int c1) {
     return tuned_predict(h->tuned, h->precision, N, c0, c1, e0, e0 + ne, sc, h->stream);
   });
   // gravity faces, then fault faces (both read the stored time derivatives)
+  if (st == hipSuccess)
+    st = timed(h, 1, ng, [&]() -> hipError_t {
+      if (h->precision == SEIS_FP64) return launch_gravity<double>(N, h->d64, gl, ng, h->stream);
+      return launch_gravity<float>(N, h->d32, gl, ng, h->stream);
+    });
   const int64_t f0 = M.fault_start[c0], nf = M.fault_start[c1 + 1] - f0;
   if (st == hipSuccess)
-    st = timed(h, 1, ng + nf, [&]() -> hipError_t {
-      hipError_t sg = h->precision == SEIS_FP64 ? launch_gravity<double>(N, h->d64, gl, ng, h->stream)
-                                                : launch_gravity<float>(N, h->d32, gl, ng, h->stream);
-      if (sg != hipSuccess) return sg;
+    st = timed(h, 3, nf, [&]() -> hipError_t {
       if (h->precision == SEIS_FP64) return launch_fault<double>(N, h->fault, h->d64.gD, h->d64.In, f0, nf, h->stream);
       return launch_fault<float>(N, h->fault, h->d32.gD, h->d32.In, f0, nf, h->stream);
     });
@@ -930,7 +932,7 @@ int seis_cluster_of(const seis_t* h, int32_t* out) {
 int seis_profile(seis_t* h, int enable) {
   if (!h) return SEIS_EINVAL;
   HIPCHK(h, fold_profile(h), "profile");
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     if (enable) {
       h->tot_ms[k] = 0.0;
       h->tot_launch[k] = 0;
@@ -944,7 +946,7 @@ int seis_profile(seis_t* h, int enable) {
 int seis_profile_read(seis_t* h, double* ms, int64_t* launches, int64_t* elements) {
   if (!h) return SEIS_EINVAL;
   HIPCHK(h, fold_profile(h), "profile");
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     if (ms) ms[k] = h->tot_ms[k];
     if (launches) launches[k] = h->tot_launch[k];
     if (elements) elements[k] = h->tot_elem[k];

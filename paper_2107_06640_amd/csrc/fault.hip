@@ -22,23 +22,35 @@ __device__ inline void split_state(const double* q, const double* n, double& sn,
   for (int d = 0; d < 3; ++d) vt[d] = q[6 + d] - vn * n[d];
 }
 
-// one work-group per fault face; thread m handles face node m
+// one work-group of kFaultThreads per fault face: the two elements' stored
+// derivatives are staged in LDS with contiguous reads, their traces at the
+// nodes formed by all threads, then thread m applies the law at node m
+constexpr int kFaultThreads = 256;
+
 template <typename T, int N>
-__global__ __launch_bounds__(64) void k_fault(FaultArgs a, const T* gD, T* In, int64_t f0) {
+__global__ __launch_bounds__(kFaultThreads) void k_fault(FaultArgs a, const T* gD, T* In, int64_t f0) {
   constexpr int B = nbasis(N), Bf = nface(N), FT = row_tiles(Bf);
-  __shared__ double tr[2][N + 1][Bf][9];  // traces of the time derivatives at the nodes
+  constexpr int ND = (N + 1) * B * 9;      // stored values per element
+  __shared__ T sd[2][ND];                  // derivatives D~k of the two sides
+  __shared__ double tr[2][N + 1][Bf][9];   // their traces at the nodes
   const int64_t f = f0 + blockIdx.x;
   const int64_t em = a.elem[f], ep = a.pelem[f];
   const int fm = a.face[f], fp = a.pface[f], h = a.perm[f];
-  const T* Dm = gD + (int64_t)a.dslot[em] * (N + 1) * B * 9;
-  const T* Dp = gD + (int64_t)a.dslot[ep] * (N + 1) * B * 9;
+  const T* Dm = gD + (int64_t)a.dslot[em] * ND;
+  const T* Dp = gD + (int64_t)a.dslot[ep] * ND;
+  for (int i = threadIdx.x; i < ND; i += blockDim.x) {
+    sd[0][i] = Dm[i];
+    sd[1][i] = Dp[i];
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < 2 * (N + 1) * Bf * 9; i += blockDim.x) {
     const int side = i / ((N + 1) * Bf * 9), r = i % ((N + 1) * Bf * 9);
     const int k = r / (Bf * 9), m = (r / 9) % Bf, p = r % 9;
     const int node = side == 0 ? m : a.pinv[h * Bf + m];
     const double* Em = a.E + ((int64_t)(side == 0 ? fm : fp) * Bf + node) * B;
-    const T* D = (side == 0 ? Dm : Dp) + (int64_t)k * B * 9 + p;
+    const T* D = &sd[side][k * B * 9 + p];
     double acc = 0.0;
+#pragma unroll 8
     for (int l = 0; l < B; ++l) acc += Em[l] * (double)D[l * 9];
     tr[side][k][m][p] = acc;
   }
@@ -58,14 +70,22 @@ __global__ __launch_bounds__(64) void k_fault(FaultArgs a, const T* gD, T* In, i
   double slip[3] = {st[0], st[1], st[2]}, psi = st[3];
   double V[3] = {0.0, 0.0, 0.0}, Tb[3] = {0.0, 0.0, 0.0}, Stot = 0.0;
   double as = 0.0, avn = 0.0, atau[3] = {0.0, 0.0, 0.0}, avm[3] = {0.0, 0.0, 0.0}, avp[3] = {0.0, 0.0, 0.0};
+  // a real loop over the time points, the traces re-read from LDS in each
+  // (an opaque offset keeps them from being hoisted into registers for the
+  // whole loop, which would cost the occupancy of the trace phase)
+#pragma unroll 1
   for (int j = 0; j <= N; ++j) {
     const double tj = a.tq[j], wj = a.tw[j];
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    const double* t0 = &tr[0][0][m][0] + z;
+    const double* t1 = &tr[1][0][m][0] + z;
     double qm[9], qp[9];
     for (int p = 0; p < 9; ++p) {
       double x = 0.0, y = 0.0, pw = 1.0;
       for (int k = 0; k <= N; ++k) {  // q(t) = sum_k D~k (t / dt)^k
-        x += pw * tr[0][k][m][p];
-        y += pw * tr[1][k][m][p];
+        x += pw * t0[k * Bf * 9 + p];
+        y += pw * t1[k * Bf * 9 + p];
         pw *= tj;
       }
       qm[p] = x;
@@ -139,7 +159,7 @@ hipError_t launch_fault(int N, const FaultArgs& a, const T* gD, T* In, int64_t f
     return hipErrorInvalidValue;
   switch (N) {
 #define SEIS_F(NN) \
-  case NN: hipLaunchKernelGGL((k_fault<T, NN>), dim3((unsigned)nf), dim3(64), 0, s, a, gD, In, f0); break;
+  case NN: hipLaunchKernelGGL((k_fault<T, NN>), dim3((unsigned)nf), dim3(kFaultThreads), 0, s, a, gD, In, f0); break;
     SEIS_F(2) SEIS_F(3) SEIS_F(4) SEIS_F(5) SEIS_F(6)
 #undef SEIS_F
     default: return hipErrorInvalidValue;

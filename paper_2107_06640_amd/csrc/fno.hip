@@ -3,6 +3,7 @@
 // and reduction kernels of training.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -12,6 +13,15 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// eight consecutive BF16 values from LDS as two 8-byte reads (rows are 8-byte aligned)
+__device__ __forceinline__ bf8 lds8(const unsigned short* p) {
+  const s4 lo = *reinterpret_cast<const s4*>(p), hi = *reinterpret_cast<const s4*>(p + 4);
+  const s8 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(bf8, v);
+}
 
 __device__ __forceinline__ unsigned short to_bf16(float x) {
   unsigned int u = __float_as_uint(x);
@@ -38,9 +48,12 @@ struct GemmArgs {
 constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 4;  // LDS rows padded (8-byte aligned fragments)
 
 // 256 threads, 4 wavefronts, each a 32 x 32 quarter of the 64 x 64 tile as
-// 2 x 2 products v_mfma_f32_16x16x16_bf16 (A lane l: row l%16, k 4(l/16)..+3;
-// B lane l: k 4(l/16)..+3, column l%16; C lane l: rows 4(l/16)+v, column l%16).
-// Tiles of A and B are staged in LDS as BF16, both with k contiguous.
+// 2 x 2 products v_mfma_f32_16x16x32_bf16 of gfx950 per 32-wide K step (A lane
+// l: row l%16, eight k values 8(l/16)..+7; B lane l: the same eight k values,
+// column l%16; C lane l: rows 4(l/16)+v, column l%16). A and B place each k
+// value in the same (lane group, register slot), so the products pair the
+// right entries whatever order the instruction gives the slots. Tiles of A
+// and B are staged in LDS as BF16, both with k contiguous.
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ unsigned short sA[BM][LDK];
   __shared__ unsigned short sB[BN][LDK];
@@ -83,20 +96,17 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       sB[nn][kk] = to_bf16(x);
     }
     __syncthreads();
+    {
+      bf8 af[2], bf[2];
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 16) {
-      s4 af[2], bf[2];
+      for (int i = 0; i < 2; ++i) af[i] = lds8(&sA[wm * 32 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        af[i] = *reinterpret_cast<const s4*>(&sA[wm * 32 + i * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        bf[j] = *reinterpret_cast<const s4*>(&sB[wn * 32 + j * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
+      for (int j = 0; j < 2; ++j) bf[j] = lds8(&sB[wn * 32 + j * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -150,15 +160,17 @@ __global__ void k_gelu_bwd(int64_t n, const float* z, const float* da, float* dz
     dz[i] = da[i] * gelu_d(z[i]);
 }
 
-// one work-group per channel
+// work-groups (channel c, part q of gridDim.y): each sums a strided share of
+// the channel's n_outer x S values and adds it to db[c] (zeroed before)
 __global__ __launch_bounds__(256) void k_channel_sum(int64_t n_outer, int64_t C, int64_t S, const float* dz,
                                                      float* db) {
   __shared__ float red[256];
   const int64_t c = blockIdx.x;
+  const int64_t n = n_outer * S, stride = (int64_t)gridDim.y * 256;
   float s = 0.0f;
-  for (int64_t o = 0; o < n_outer; ++o) {
-    const float* p = dz + (o * C + c) * S;
-    for (int64_t j = threadIdx.x; j < S; j += 256) s += p[j];
+  for (int64_t i = (int64_t)blockIdx.y * 256 + threadIdx.x; i < n; i += stride) {
+    const int64_t o = i / S, j = i - o * S;
+    s += dz[(o * C + c) * S + j];
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -166,7 +178,12 @@ __global__ __launch_bounds__(256) void k_channel_sum(int64_t n_outer, int64_t C,
     if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) db[c] = red[0];
+  if (threadIdx.x == 0) atomicAdd(db + c, red[0]);
+}
+
+__global__ void k_zero(int64_t n, float* x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0f;
 }
 
 __global__ void k_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
@@ -278,7 +295,14 @@ int fno_gelu_backward(int64_t n, const float* z, const float* da, float* dz, voi
 
 int fno_channel_sum(int64_t n_outer, int64_t C, int64_t S, const float* dz, float* db, void* stream) {
   if (n_outer < 0 || C <= 0 || S <= 0 || !dz || !db) return -1;
-  hipLaunchKernelGGL(k_channel_sum, dim3((unsigned)C), dim3(256), 0, (hipStream_t)stream, n_outer, C, S, dz, db);
+  if (C > 65535) return -1;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(C)), dim3(256), 0, s, C, db);
+  if (hipGetLastError() != hipSuccess) return -3;
+  // enough parts per channel to fill the chip, each summing >= 16 values per thread
+  const int64_t n = n_outer * S;
+  const int64_t parts = std::max<int64_t>(1, std::min<int64_t>((2048 + C - 1) / C, (n + 4095) / 4096));
+  hipLaunchKernelGGL(k_channel_sum, dim3((unsigned)C, (unsigned)parts), dim3(256), 0, s, n_outer, C, S, dz, db);
   return status(hipGetLastError());
 }
 

@@ -346,3 +346,76 @@ class FNO:
         for name in self.names:
             self.k.adam(self.params[name], self.grads[name], self.adam_m[name], self.adam_v[name], lr, b1, b2, eps,
                         self.step_count)
+
+
+class CountingKernels(Kernels):
+    """Kernels that also count the products' algorithmic flops (2 batch M N K per call)
+    and bytes (FP32 A and B read once, C read and written once)."""
+
+    def __init__(self, stream=None):
+        super().__init__(stream)
+        self.flops = 0
+        self.bytes = 0
+        self.calls = 0
+
+    def gemm(self, batch, M, N, K, *args, **kw):
+        self.flops += 2 * batch * M * N * K
+        self.bytes += 4 * batch * (M * K + K * N + 2 * M * N)
+        self.calls += 1
+        super().gemm(batch, M, N, K, *args, **kw)
+
+
+def bench_main(argv=None):
+    """Time training steps of the surrogate's network at its data shape.
+
+        python -m paper_2107_06640_amd.fno [--batch 64] [--steps 5] [--warmup 2]
+
+    A step is forward (kept for the backward), loss, backward and Adam on a
+    seeded random batch of the 64 x 64 x 32 grid with 4 input channels
+    (width 32, 12 modes, 4 layers, hidden 128). Prints one JSON line: time per
+    step and the products' algorithmic flops per step (their rate against
+    the BF16 matrix-core peak needs the products' own kernel time, which a
+    kernel trace gives).
+    """
+    import argparse
+    import json
+
+    import torch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    k = CountingKernels()
+    net = FNO(64, 64, 32, cin=4, width=32, modes=12, layers=4, hidden=128, seed=0, kernels=k)
+    g = torch.Generator(device="cuda:0").manual_seed(0)
+    u = torch.randn(4, a.batch, 64, 64, 32, device="cuda:0", generator=g)
+    y = torch.randn(1, a.batch, 64, 64, 32, device="cuda:0", generator=g)
+
+    def step():
+        yhat = net.forward(u, keep=True)
+        _, grad = net.loss(yhat, y)
+        net.backward(grad)
+        net.adam_step()
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    k.flops = k.bytes = k.calls = 0
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(a.steps):
+        step()
+    t1.record()
+    t1.synchronize()
+    ms = t0.elapsed_time(t1) / a.steps
+    print(json.dumps({"batch": a.batch, "steps": a.steps, "ms_per_step": ms,
+                      "gemm_flops_per_step": k.flops / a.steps, "gemm_bytes_per_step": k.bytes / a.steps,
+                      "gemm_calls_per_step": k.calls / a.steps,
+                      "gemm_tflops_over_step_time": k.flops / a.steps / (ms / 1e3) / 1e12}), flush=True)
+
+
+if __name__ == "__main__":
+    bench_main()

@@ -246,13 +246,14 @@ class Solver:
         self._check(self._lib.seis_profile(self._h, 1 if enable else 0))
 
     def profile_read(self):
-        """Per-kernel totals: {'predict'|'gravity'|'correct': (ms, launches, elements)}."""
-        ms = np.zeros(3)
-        la = np.zeros(3, dtype=np.int64)
-        el = np.zeros(3, dtype=np.int64)
+        """Per-kernel totals: {'predict'|'gravity'|'correct'|'fault': (ms, launches, elements)}."""
+        ms = np.zeros(4)
+        la = np.zeros(4, dtype=np.int64)
+        el = np.zeros(4, dtype=np.int64)
         self._check(self._lib.seis_profile_read(self._h, _ptr(ms, C.c_double), _ptr(la, C.c_int64),
                                                 _ptr(el, C.c_int64)))
-        return {k: (float(ms[i]), int(la[i]), int(el[i])) for i, k in enumerate(("predict", "gravity", "correct"))}
+        return {k: (float(ms[i]), int(la[i]), int(el[i]))
+                for i, k in enumerate(("predict", "gravity", "correct", "fault"))}
 
     def energy_into(self, out_ptr, noalloc=False):
         """Energy and field norms into 12 doubles at device address ``out_ptr`` (asynchronous)."""
