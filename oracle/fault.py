@@ -22,6 +22,17 @@ Readings (the paper defers the friction law's details to its references):
   * linear slip weakening, the law of the paper's benchmark (Sec. 6.2):
     f = mu_s - (mu_s - mu_d) min(psi / D_c, 1) with psi the slip path,
     dpsi/dt = |V|;
+  * rate-and-state friction with fast velocity weakening, the law of the
+    Palu run (Sec. 6.3), in its usual regularised form:
+        f(V, psi) = a asinh(V / (2 V0) exp(psi / a)),
+        dpsi/dt = -(V / L)(psi - psi_ss(V)),
+        psi_ss(V) = a ln(2 V0 / V sinh(f_ss(V) / a)),
+        f_ss(V) = f_w + (f_LV(V) - f_w) / (1 + (V / V_w)^8)^(1/8),
+        f_LV(V) = f0 - (b - a) ln(V / V0);
+    the fault always slips: V >= 0 solves |T| - eta V = f(V, psi) max(0, -s)
+    (T the total shear traction of the locked state), and over a part of the
+    step of length h at that V the state relaxes exactly toward psi_ss(V):
+    psi <- psi_ss + (psi - psi_ss) exp(-V h / L);
   * the normal stress and the normal velocity are those of the welded
     interface (Godunov middle state, Sec. 4.2); the shear traction follows from
     the S-wave characteristics of each side,
@@ -39,8 +50,12 @@ import numpy as np
 
 from .riemann import split
 
-# fault parameters per face: s0, tau0 (x, y, z), mu_s, mu_d, D_c, C
-N_PARAMS = 8
+# fault parameters per face (16): s0, tau0 (x, y, z), then the law's:
+#   slip weakening (law 0): mu_s, mu_d, D_c, C
+#   rate and state (law 1): a, b, L, V0, f0, f_w, V_w, psi0
+# and the law at index 15
+N_PARAMS = 16
+LAW_SLIP_WEAKENING, LAW_RATE_STATE = 0, 1
 
 
 def friction_coefficient(psi, mu_s, mu_d, dc):
@@ -48,16 +63,47 @@ def friction_coefficient(psi, mu_s, mu_d, dc):
     return mu_s - (mu_s - mu_d) * np.minimum(psi / dc, 1.0)
 
 
-def fault_state(qm, qp, n, matm, matp, params, psi):
+def rs_friction(V, psi, a, V0):
+    """Rate-and-state friction coefficient a asinh(V / (2 V0) exp(psi / a))."""
+    return a * np.arcsinh(V / (2.0 * V0) * np.exp(psi / a))
+
+
+def rs_steady_state(V, a, b, V0, f0, fw, Vw):
+    """psi_ss(V) of fast velocity weakening."""
+    fLV = f0 - (b - a) * np.log(V / V0)
+    fss = fw + (fLV - fw) / (1.0 + (V / Vw) ** 8) ** 0.125
+    return a * np.log(2.0 * V0 / V * np.sinh(fss / a))
+
+
+def rs_slip_rate(T, sigma, eta, psi, a, V0, iters=200):
+    """Root V in [0, T / eta] of T - eta V - sigma a asinh(V / (2 V0) exp(psi / a)), by bisection.
+
+    The left side falls strictly with V; bisection to the FP64 resolution of
+    the bracket (the library solves the same equation by safeguarded Newton).
+    """
+    lo = np.zeros_like(T)
+    hi = T / eta
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        g = T - eta * mid - sigma * rs_friction(mid, psi, a, V0)
+        lo = np.where(g > 0, mid, lo)
+        hi = np.where(g > 0, hi, mid)
+    return 0.5 * (lo + hi)
+
+
+def fault_state(qm, qp, n, matm, matp, params, psi, h=0.0):
     """Middle state of a fault point (see the module notes).
 
     qm, qp: [..., 9] states of the two sides; n: [..., 3] unit normal from - to
     +; matm, matp: (lam, mu, rho) arrays broadcastable to qm[..., 0];
-    params: [..., 8] fault parameters; psi: [...] slip path so far.
+    params: [..., 16] fault parameters; psi: [...] slip path (slip
+    weakening) or state (rate and state) so far; h: the length of step this
+    point stands for (the rate-and-state state relaxes over it).
     Returns a dict: s (normal stress of the middle state, perturbation),
     vn (normal velocity), tau (shear traction, perturbation), vm, vp
     (tangential velocities of the two sides), V (slip rate), T (total shear
-    traction), S (total normal stress).
+    traction), S (total normal stress), psi (the state after the point:
+    for slip weakening unchanged, the caller adds |V| h).
     """
     lm, mm, rm = matm
     lp, mp, rp = matp
@@ -74,18 +120,33 @@ def fault_state(qm, qp, n, matm, matp, params, psi):
     s0 = params[..., 0]
     tau0 = params[..., 1:4]
     tau0 = tau0 - np.einsum("...i,...i->...", tau0, n)[..., None] * n  # the shear part only
-    mu_s, mu_d, dc, coh = (params[..., k] for k in range(4, 8))
     S = s0 + s
-    strength = coh + friction_coefficient(psi, mu_s, mu_d, dc) * np.maximum(0.0, -S)
     T = tau0 + lock
     mag = np.sqrt(np.einsum("...i,...i->...", T, T))
-    slip = mag > strength
-    # below the strength the point is locked: tau = tau_lock and V = 0 exactly
-    # (|tau| < tau_S in tau_S V = tau |V| leaves only V = 0)
+    law = params[..., 15]
+    rs = law == LAW_RATE_STATE
+    # slip weakening: locked below the strength (tau = tau_lock and V = 0
+    # exactly: |tau| < tau_S in tau_S V = tau |V| leaves only V = 0), else at it
+    mu_s, mu_d, dc, coh = (params[..., k] for k in range(4, 8))
+    strength = coh + friction_coefficient(psi, mu_s, mu_d, np.where(rs, 1.0, dc)) * np.maximum(0.0, -S)
+    slip = (mag > strength) & ~rs
     ratio = np.where(slip, strength / np.where(slip, mag, 1.0), 1.0)
+    # rate and state: always sliding, |T| - eta V at the rate-dependent strength
+    a, b, L, V0, f0, fw, Vw = (params[..., k] for k in range(4, 11))
+    a1, V01 = np.where(rs, a, 1.0), np.where(rs, V0, 1.0)
+    vrs = rs_slip_rate(np.where(rs, mag, 0.0), np.maximum(0.0, -S), eta, np.where(rs, psi, 0.0), a1, V01)
+    ratio = np.where(rs, np.where(mag > 0, (mag - eta * vrs) / np.where(mag > 0, mag, 1.0), 1.0), ratio)
+    moving = slip | rs
     Tb = ratio[..., None] * T
-    tau = np.where(slip[..., None], Tb - tau0, lock)
-    V = np.where(slip[..., None], (lock - tau) / eta[..., None], 0.0)
+    tau = np.where(moving[..., None], Tb - tau0, lock)
+    V = np.where(moving[..., None], (lock - tau) / eta[..., None], 0.0)
+    speed = np.sqrt(np.einsum("...i,...i->...", V, V))
+    # state of rate and state over the point's share h of the step, at that slip rate
+    vpos = np.where(rs & (speed > 0), speed, 1.0)
+    pss = rs_steady_state(vpos, a1, np.where(rs, b, 1.0), V01, np.where(rs, f0, 1.0), np.where(rs, fw, 1.0),
+                          np.where(rs, Vw, 1.0))
+    psi_rs = np.where(speed > 0, pss + (psi - pss) * np.exp(-speed * h / np.where(rs, L, 1.0)), psi)
+    psi_new = np.where(rs, psi_rs, psi)
     vm = vtm + (tau - ttm) / zsm[..., None]
     vp = vtp - (tau - ttp) / zsp[..., None]
-    return dict(s=s, vn=vn, tau=tau, vm=vm, vp=vp, V=V, T=Tb, S=S)
+    return dict(s=s, vn=vn, tau=tau, vm=vm, vp=vp, V=V, T=Tb, S=S, psi=psi_new, rs=rs)

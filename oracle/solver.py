@@ -38,7 +38,7 @@ from . import quadrature as quad
 from .mesh import Geometry, adjacency, ref_face_points, FACE_VERTS
 from .physics import jacobians, stress_tensor
 from .riemann import godunov_flux, ghost_state, gravity_eta_step, flux_of_state
-from .fault import N_PARAMS, fault_state
+from .fault import LAW_RATE_STATE, LAW_SLIP_WEAKENING, N_PARAMS, fault_state
 
 FACE_INTERIOR, FACE_PERIODIC, FACE_GRAVITY, FACE_ABSORBING, FACE_WALL, FACE_FREE, FACE_VELOCITY, FACE_FAULT = range(8)
 
@@ -208,10 +208,20 @@ class Oracle:
         self.fault_traction = np.zeros((nF, nf, 3))
         self.fault_normal = np.zeros((nF, nf))
 
-    def set_fault(self, params):
-        """Fault parameters [F, 8] per face: s0, tau0 (3), mu_s, mu_d, D_c, C."""
+    def set_fault(self, params, law=LAW_SLIP_WEAKENING):
+        """Fault parameters per face and the fault at rest (no slip, initial state).
+
+        law 0 (slip weakening): params [F, 8] = s0, tau0 (3), mu_s, mu_d, D_c, C;
+        law 1 (rate and state): params [F, 12] = s0, tau0 (3), a, b, L, V0, f0, f_w, V_w, psi0.
+        """
         p = np.asarray(params, dtype=np.float64)
-        self.fault_params[:] = np.broadcast_to(p, self.fault_params.shape)
+        k = 8 if law == LAW_SLIP_WEAKENING else 12
+        self.fault_params[:] = 0.0
+        self.fault_params[:, :k] = np.broadcast_to(p, (self.fault_params.shape[0], k))
+        self.fault_params[:, 15] = law
+        self.fault_slip[:] = 0.0
+        self.fault_rate[:] = 0.0
+        self.fault_psi[:] = self.fault_params[:, 11][:, None] if law == LAW_RATE_STATE else 0.0
 
     def _fault_fluxes(self, c, own, dt):
         """Face-flux updates of the fault faces of cluster c over its step of length dt.
@@ -247,11 +257,11 @@ class Oracle:
             powk = t ** np.arange(N + 1) / fact                              # q(t) = sum_k D_k t^k / k!
             qm = ein("k,mkqp->mqp", powk, tr[0])
             qp = ein("k,mkqp->mqp", powk, tr[1])
-            st = fault_state(qm, qp, n, matm, matp, prm, psi)
+            st = fault_state(qm, qp, n, matm, matp, prm, psi, h=w)
             for k in acc:
                 acc[k] = acc[k] + w * st[k]
             speed = np.sqrt(np.einsum("...i,...i->...", st["V"], st["V"]))
-            psi = psi + w * speed
+            psi = np.where(st["rs"], st["psi"], psi + w * speed)
             slip = slip + w * st["V"]
         self.fault_psi[sel] = psi
         self.fault_slip[sel] = slip

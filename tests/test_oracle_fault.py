@@ -17,6 +17,11 @@
 * Clusters: across a fault face the two sides share a cluster; the
   assignment equals min_J (raw c_J + d(K, J)) with fault faces at distance 0
   (brute force).
+* Rate-and-state friction (fast velocity weakening): the law's textbook
+  limits (steady state, low-velocity logarithmic law, the weakened f_w); a
+  fault started at steady-state sliding keeps sliding at that rate with its
+  state unchanged over the first step; on the planar fault the slip follows
+  the one-variable ODE of radiation damping, integrated with DOP853.
 """
 import numpy as np
 import pytest
@@ -136,3 +141,89 @@ def test_fault_face_must_meet_a_fault_face():
     fk[e, f] = inputs.FACE_INTERIOR
     with pytest.raises(ValueError):
         adjacency(mesh.tet, fk, mesh.xyz, mesh.period)
+
+
+# ---------------------------------------------------------------------------
+# rate-and-state friction (fast velocity weakening)
+RS = dict(a=0.01, b=0.014, L=0.2, V0=1e-6, f0=0.6, fw=0.2, Vw=0.1)
+
+
+def test_rate_state_law_textbook_limits():
+    """f(V, psi_ss(V)) = f_ss(V); f_ss -> f0 - (b - a) ln(V/V0) for V << V_w and -> f_w for V >> V_w;
+    for V/V0 exp(psi/a) >> 1 the regularised law is the classic a ln(V/V0) + psi."""
+    from oracle.fault import rs_friction, rs_steady_state
+    p = RS
+    V = np.logspace(-12, 2, 29)
+    pss = rs_steady_state(V, p["a"], p["b"], p["V0"], p["f0"], p["fw"], p["Vw"])
+    f = rs_friction(V, pss, p["a"], p["V0"])
+    fLV = p["f0"] - (p["b"] - p["a"]) * np.log(V / p["V0"])
+    fss = p["fw"] + (fLV - p["fw"]) / (1.0 + (V / p["Vw"]) ** 8) ** 0.125
+    assert np.allclose(f, fss, rtol=1e-12, atol=1e-14)
+    slow = V < 1e-4
+    assert np.allclose(f[slow], fLV[slow], rtol=1e-9)
+    assert abs(f[-1] - p["fw"]) < 1e-3
+    psi = 0.55
+    Vb = np.array([1e-3, 1e-1, 1.0])
+    assert np.allclose(rs_friction(Vb, psi, p["a"], p["V0"]), p["a"] * np.log(Vb / p["V0"]) + psi, rtol=1e-9)
+
+
+def rs_case(Vi, sig=50e6, tau0=30e6):
+    """Background traction in equilibrium with slip rate Vi at the first step: psi0 from
+    tau0 - eta Vi = sig a asinh(Vi / (2 V0) exp(psi0 / a))."""
+    p = RS
+    eta = Z / 2.0
+    psi0 = p["a"] * np.log(2 * p["V0"] / Vi * np.sinh((tau0 - eta * Vi) / (sig * p["a"])))
+    return [-sig, tau0, 0.0, 0.0, p["a"], p["b"], p["L"], p["V0"], p["f0"], p["fw"], p["Vw"], psi0]
+
+
+def test_rate_state_steady_sliding_first_step():
+    """State at steady state psi_ss(Vi) and background traction sig f_ss(Vi) + eta Vi (in the
+    law's own terms: f_LV and the V_w cut-off written out here): from rest the fault slides at
+    Vi over the whole first step and the state does not move."""
+    p = RS
+    Vi, sig = 0.3, 50e6
+    fLV = p["f0"] - (p["b"] - p["a"]) * np.log(Vi / p["V0"])
+    fss = p["fw"] + (fLV - p["fw"]) / (1.0 + (Vi / p["Vw"]) ** 8) ** 0.125
+    psi0 = p["a"] * np.log(2 * p["V0"] / Vi * np.sinh(fss / p["a"]))
+    tau0 = sig * fss + Z / 2.0 * Vi
+    mesh, mats = planar()
+    o = oracle_for(mesh, mats, 3)
+    o.set_fault([-sig, tau0, 0.0, 0.0, p["a"], p["b"], p["L"], p["V0"], p["f0"], p["fw"], p["Vw"], psi0], law=1)
+    o.run(1)
+    assert np.abs(o.fault_rate[..., 0] / Vi - 1.0).max() < 1e-10
+    assert np.abs(o.fault_rate[..., 1:]).max() < 1e-12
+    assert np.abs(o.fault_psi - psi0).max() < 1e-12
+    assert np.abs(o.fault_slip[..., 0] / (Vi * o.time) - 1.0).max() < 1e-10
+
+
+def test_rate_state_planar_fault_against_ode():
+    """The planar stress-drop problem reduces to one ODE (radiation damping tau0 - Z V / 2 at
+    the fault): integrated with DOP853 it gives the slip the DG solution must follow."""
+    from scipy.integrate import solve_ivp
+    from oracle.fault import rs_slip_rate, rs_steady_state
+    p = RS
+    prm = rs_case(0.3)
+    sig, tau0, psi0 = -prm[0], prm[1], prm[11]
+    eta = Z / 2.0
+
+    def vel(psi):
+        return float(rs_slip_rate(np.array([tau0]), np.array([sig]), eta, np.array([psi]), p["a"], p["V0"])[0])
+
+    def rhs(t, y):
+        V = vel(y[0])
+        pss = float(rs_steady_state(np.array(V), p["a"], p["b"], p["V0"], p["f0"], p["fw"], p["Vw"]))
+        return [-(V / p["L"]) * (y[0] - pss), V]
+
+    sol = solve_ivp(rhs, (0.0, 0.3), [psi0, 0.0], method="DOP853", rtol=1e-10, atol=1e-13, dense_output=True)
+    mesh, mats = planar()
+    o = oracle_for(mesh, mats, 4)
+    o.set_fault(prm, law=1)
+    checked = 0
+    while o.time < 0.3:
+        o.run(1)
+        if o.time > 0.1:
+            want = sol.sol(o.time)[1]
+            assert abs(o.fault_slip[..., 0].mean() / want - 1.0) < 0.03
+            checked += 1
+    assert checked > 10
+    assert vel(sol.sol(0.3)[0]) > 3.0  # the fault has weakened: 0.3 -> 3.9 m/s
