@@ -193,30 +193,44 @@ int seis_write(seis_t *h, const double *dofs, const double *eta);
  * Synchronises the stream; n = 0 removes the forcing. Errors: SEIS_EINVAL. */
 int seis_set_uplift(seis_t *h, int n, const double *src);
 
+enum {
+  SEIS_FRICTION_SLIP_WEAKENING = 0, /* linear slip weakening (the benchmark's law, Sec. 6.2) */
+  SEIS_FRICTION_RATE_STATE = 1      /* rate and state, fast velocity weakening (the Palu run's law) */
+};
+
 /* Friction of the SEIS_FACE_FAULT faces (Sec. 3, fault boundary condition:
- * |tau| <= tau_S, slip parallel to tau where |tau| = tau_S; linear slip
- * weakening as in the benchmark of Sec. 6.2). A fault face is listed once,
- * from its '-' side, the element with the smaller id; n points from '-' to
- * '+'; faces are ordered by ('-' element, local face); n must equal
- * seis_info's n_fault_faces. params [n][8], host memory, per face:
+ * |tau| <= tau_S, slip parallel to tau where |tau| = tau_S). A fault face is
+ * listed once, from its '-' side, the element with the smaller id; n points
+ * from '-' to '+'; faces are ordered by ('-' element, local face); n must
+ * equal seis_info's n_fault_faces. params, host memory, per face first
  *   s0       background normal stress (Pa, negative in compression),
  *   tau0[3]  background traction (Pa; its normal part is ignored),
- *   mu_s, mu_d, D_c  friction f = mu_s - (mu_s - mu_d) min(psi / D_c, 1) with
- *            psi the slip path (m), D_c > 0,
- *   C        cohesion (Pa, >= 0; INFINITY keeps the face locked).
- * Strength tau_S = C + f max(0, -(s0 + s)) with s the normal stress of the
- * elements' state; the fault slips where |tau0 + tau| would exceed it.
- * Until this is called every fault face is locked (a welded interface).
- * Changes no slip state. Errors: SEIS_EINVAL (n, a parameter out of range). */
-int seis_set_fault(seis_t *h, int64_t n, const double *params);
+ * then, for law SEIS_FRICTION_SLIP_WEAKENING ([n][8]):
+ *   mu_s, mu_d, D_c  f = mu_s - (mu_s - mu_d) min(psi / D_c, 1), psi the slip
+ *            path (m), D_c > 0,
+ *   C        cohesion (Pa, >= 0; INFINITY keeps the face locked);
+ *   strength tau_S = C + f max(0, -(s0 + s)) with s the normal stress of the
+ *   elements' state; the fault slips where |tau0 + tau| would exceed it;
+ * or, for law SEIS_FRICTION_RATE_STATE ([n][12]):
+ *   a, b, L, V0, f0, f_w, V_w, psi0 of f(V, psi) = a asinh(V / (2 V0) e^(psi / a)),
+ *   dpsi/dt = -(V / L)(psi - psi_ss(V)), psi_ss(V) = a ln(2 V0 / V sinh(f_ss(V) / a)),
+ *   f_ss(V) = f_w + (f0 - (b - a) ln(V / V0) - f_w) / (1 + (V / V_w)^8)^(1/8);
+ *   psi0 the initial state; the fault always slides, with
+ *   |tau0 + tau| = f(|V|, psi) max(0, -(s0 + s)) + eta |V|.
+ * The law is applied at the fault's points at the Gauss-Legendre points of
+ * each step (the state advanced after each). Until this is called every
+ * fault face is locked (a welded interface). Puts the fault at rest (no
+ * slip, psi = 0 or psi0). Errors: SEIS_EINVAL (n, law, a parameter out of
+ * range). */
+int seis_set_fault(seis_t *h, int64_t n, int law, const double *params);
 
 /* Fault state at the fault's points: out [n_fault_faces][(N+1)(N+2)/2][14]
  * (host, caller-owned), per point: x, y, z, slip (3, m, v+ - v- integrated
- * over time), slip path psi (m), slip rate V (3, m/s, at the last time point
- * of the last step), total shear traction tau0 + tau (3, Pa), total normal
- * stress s0 + s (Pa). Points are the face's equispaced lattice nodes; match
- * them by their coordinates. seis_write resets slip, psi and the rates to
- * zero. Synchronises the stream. */
+ * over time), psi (the slip path, m, or the rate-and-state state), slip rate
+ * V (3, m/s, at the last time point of the last step), total shear traction
+ * tau0 + tau (3, Pa), total normal stress s0 + s (Pa). Points are the face's
+ * equispaced lattice nodes; match them by their coordinates. seis_write and
+ * seis_set_fault put the fault at rest. Synchronises the stream. */
 int seis_fault_read(seis_t *h, double *out);
 
 /* ADER predictor of every element of cluster c for its next step (Sec. 4.1,

@@ -88,6 +88,7 @@ struct seis_t {
   FaultArgs fault{};
   double* fault_par = nullptr;
   double* fault_state = nullptr;
+  std::vector<double> fault_par_host;  // [F][kFaultParams], library order
   double* uplift_src = nullptr;
   int64_t* macro_dev = nullptr;
   // output point sets: seis_points (ids 0, 1, ...), and the sea surface and
@@ -242,6 +243,7 @@ int build_common(seis_t* h, DevData<double>& c) {
       par[k * kFaultParams + 7] = INFINITY;
     }
     HIPCHK(h, upload(b, &h->fault_par, par), "upload fault parameters");
+    h->fault_par_host = par;
     const int64_t ns = std::max<int64_t>(F, 1) * M.Bf * kFaultState;
     HIPCHK(h, b.alloc(&h->fault_state, ns), "alloc fault state");
     HIPCHK(h, hipMemset(h->fault_state, 0, ns * sizeof(double)), "clear fault state");
@@ -372,6 +374,24 @@ hipError_t timed(seis_t* h, int kind, int64_t n, F fn) {
   if (st != hipSuccess) return st;
   h->recs.push_back({kind, a, b, n});
   return hipSuccess;
+}
+
+// Faults at rest: no slip, slip rates zero, the friction state at its start
+// (slip path 0; the rate-and-state state psi0 of the face).
+int reset_faults(seis_t* h) {
+  const Model& M = h->M;
+  const int64_t F = (int64_t)M.f_elem.size();
+  if (F == 0) return SEIS_OK;
+  std::vector<double> st(F * M.Bf * kFaultState, 0.0);
+  for (int64_t f = 0; f < F; ++f) {
+    const double* q = h->fault_par_host.data() + f * kFaultParams;
+    if (q[15] == double(kLawRateState))
+      for (int m = 0; m < M.Bf; ++m) st[(f * M.Bf + m) * kFaultState + 3] = q[11];
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
+  HIPCHK(h, hipMemcpy(h->fault_state, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice),
+         "reset fault state");
+  return SEIS_OK;
 }
 
 Sched make_sched(const seis_t* h) {
@@ -610,10 +630,11 @@ int seis_write(seis_t* h, const double* dofs, const double* eta) {
            "write eta");
   }
   // a written state starts a new run at time 0 (the clock of the uplift
-  // forcing) with the faults at rest (no slip)
-  if (!M.f_elem.empty())
-    HIPCHK(h, hipMemset(h->fault_state, 0, M.f_elem.size() * M.Bf * kFaultState * sizeof(double)),
-           "clear fault state");
+  // forcing) with the faults at rest (no slip, the friction state initial)
+  {
+    const int rc = reset_faults(h);
+    if (rc != SEIS_OK) return rc;
+  }
   const int64_t zero = 0;
   HIPCHK(h, hipMemcpy(h->macro_dev, &zero, sizeof(zero), hipMemcpyHostToDevice), "reset macro counter");
   h->macro_done = 0;
@@ -621,23 +642,34 @@ int seis_write(seis_t* h, const double* dofs, const double* eta) {
   return SEIS_OK;
 }
 
-int seis_set_fault(seis_t* h, int64_t n, const double* params) {
+int seis_set_fault(seis_t* h, int64_t n, int law, const double* params) {
   if (!h) return SEIS_EINVAL;
   const Model& M = h->M;
   const int64_t F = (int64_t)M.f_elem.size();
   if (n != F || (F > 0 && !params)) return fail(h, SEIS_EINVAL, "seis_set_fault: n must equal the number of fault faces");
+  if (law != SEIS_FRICTION_SLIP_WEAKENING && law != SEIS_FRICTION_RATE_STATE)
+    return fail(h, SEIS_EINVAL, "seis_set_fault: unknown friction law");
+  const int np = law == SEIS_FRICTION_SLIP_WEAKENING ? 8 : 12;
   std::vector<double> par(std::max<int64_t>(F, 1) * kFaultParams, 0.0);
   for (int64_t k = 0; k < F; ++k) {
-    const double* p = params + k * kFaultParams;
-    if (!(p[4] >= 0.0) || !(p[5] >= 0.0) || !(p[6] > 0.0) || !(p[7] >= 0.0))
+    const double* p = params + k * np;
+    if (law == SEIS_FRICTION_SLIP_WEAKENING &&
+        (!(p[4] >= 0.0) || !(p[5] >= 0.0) || !(p[6] > 0.0) || !(p[7] >= 0.0)))
       return fail(h, SEIS_EINVAL, "seis_set_fault: need mu_s, mu_d >= 0, D_c > 0, C >= 0");
-    for (int i = 0; i < kFaultParams; ++i) par[M.fault_abi[k] * kFaultParams + i] = p[i];
+    if (law == SEIS_FRICTION_RATE_STATE &&
+        (!(p[4] > 0.0) || !(p[6] > 0.0) || !(p[7] > 0.0) || !(p[10] > 0.0) || !std::isfinite(p[5]) ||
+         !std::isfinite(p[8]) || !std::isfinite(p[9]) || !std::isfinite(p[11])))
+      return fail(h, SEIS_EINVAL, "seis_set_fault: need a, L, V0, V_w > 0 and finite b, f0, f_w, psi0");
+    double* q = par.data() + M.fault_abi[k] * kFaultParams;
+    for (int i = 0; i < np; ++i) q[i] = p[i];
+    q[15] = law;
   }
   HIPCHK(h, hipStreamSynchronize(h->stream), "sync");
   if (F > 0)
     HIPCHK(h, hipMemcpy(h->fault_par, par.data(), F * kFaultParams * sizeof(double), hipMemcpyHostToDevice),
            "write fault parameters");
-  return SEIS_OK;
+  h->fault_par_host = par;
+  return reset_faults(h);
 }
 
 int seis_fault_read(seis_t* h, double* out) {

@@ -22,6 +22,39 @@ __device__ inline void split_state(const double* q, const double* n, double& sn,
   for (int d = 0; d < 3; ++d) vt[d] = q[6 + d] - vn * n[d];
 }
 
+// rate and state: the slip rate V in [0, T / eta] with
+// T - eta V = sigma a asinh(V / (2 V0) e^(psi / a)), whose left side falls
+// strictly with V; Newton steps kept inside a shrinking bracket (bisection
+// where a step leaves it)
+__device__ inline double rs_slip_rate(double T, double sigma, double eta, double psi, double a, double V0,
+                                      double Vguess) {
+  double lo = 0.0, hi = T / eta;
+  const double c = exp(psi / a) / (2.0 * V0);
+  double V = fmin(fmax(Vguess, lo), hi);
+  for (int it = 0; it < 100; ++it) {
+    const double x = c * V;
+    const double g = T - eta * V - sigma * a * asinh(x);
+    if (g > 0.0) lo = V; else hi = V;
+    const double dg = -eta - sigma * a * c / sqrt(1.0 + x * x);
+    double Vn = V - g / dg;
+    if (!(Vn > lo && Vn < hi)) Vn = 0.5 * (lo + hi);
+    if (fabs(Vn - V) <= 1e-15 * fmax(fabs(V), 1e-300) || hi - lo <= 1e-15 * fmax(hi, 1e-300)) {
+      V = Vn;
+      break;
+    }
+    V = Vn;
+  }
+  return V;
+}
+
+__device__ inline double rs_steady_state(double V, const double* r) {
+  // r: a, b, L, V0, f0, f_w, V_w
+  const double fLV = r[4] - (r[1] - r[0]) * log(V / r[3]);
+  const double q = V / r[6], q2 = q * q, q4 = q2 * q2;
+  const double fss = r[5] + (fLV - r[5]) / pow(1.0 + q4 * q4, 0.125);
+  return r[0] * log(2.0 * r[3] / V * sinh(fss / r[0]));
+}
+
 // one work-group of kFaultThreads per fault face: the two elements' stored
 // derivatives are staged in LDS with contiguous reads, their traces at the
 // nodes formed by all threads, then thread m applies the law at node m
@@ -65,10 +98,11 @@ __global__ __launch_bounds__(kFaultThreads) void k_fault(FaultArgs a, const T* g
   const double t0n = pr[1] * n[0] + pr[2] * n[1] + pr[3] * n[2];
   const double tau0[3] = {pr[1] - t0n * n[0], pr[2] - t0n * n[1], pr[3] - t0n * n[2]};
   const double mu_s = pr[4], mu_d = pr[5], dc = pr[6], coh = pr[7];
+  const bool rate_state = pr[15] == double(kLawRateState);
   const double eta = zsm * zsp / (zsm + zsp);
   double* st = a.state + (f * Bf + m) * kFaultState;
   double slip[3] = {st[0], st[1], st[2]}, psi = st[3];
-  double V[3] = {0.0, 0.0, 0.0}, Tb[3] = {0.0, 0.0, 0.0}, Stot = 0.0;
+  double V[3] = {st[4], st[5], st[6]}, Tb[3] = {0.0, 0.0, 0.0}, Stot = 0.0;  // V: the last slip rate
   double as = 0.0, avn = 0.0, atau[3] = {0.0, 0.0, 0.0}, avm[3] = {0.0, 0.0, 0.0}, avp[3] = {0.0, 0.0, 0.0};
   // a real loop over the time points, the traces re-read from LDS in each
   // (an opaque offset keeps them from being hoisted into registers for the
@@ -102,12 +136,22 @@ __global__ __launch_bounds__(kFaultThreads) void k_fault(FaultArgs a, const T* g
       Ttot[d] = tau0[d] + lock[d];
     }
     Stot = s0 + s;
-    const double fr = mu_s - (mu_s - mu_d) * fmin(psi / dc, 1.0);
-    const double strength = coh + fr * fmax(0.0, -Stot);
     const double mag = sqrt(Ttot[0] * Ttot[0] + Ttot[1] * Ttot[1] + Ttot[2] * Ttot[2]);
-    // below the strength the point is locked: tau = tau_lock, V = 0 exactly
-    const bool slips = mag > strength;
-    const double ratio = slips ? strength / mag : 1.0;
+    bool slips;
+    double ratio;
+    if (rate_state) {
+      // always sliding, at the rate-dependent strength
+      const double v = rs_slip_rate(mag, fmax(0.0, -Stot), eta, psi, pr[4], pr[7],
+                                    sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2]));
+      slips = true;
+      ratio = mag > 0.0 ? (mag - eta * v) / mag : 1.0;
+    } else {
+      // below the strength the point is locked: tau = tau_lock, V = 0 exactly
+      const double fr = mu_s - (mu_s - mu_d) * fmin(psi / dc, 1.0);
+      const double strength = coh + fr * fmax(0.0, -Stot);
+      slips = mag > strength;
+      ratio = slips ? strength / mag : 1.0;
+    }
     double speed2 = 0.0;
     for (int d = 0; d < 3; ++d) {
       Tb[d] = ratio * Ttot[d];
@@ -121,7 +165,13 @@ __global__ __launch_bounds__(kFaultThreads) void k_fault(FaultArgs a, const T* g
     }
     as += wj * s;
     avn += wj * vn;
-    psi += wj * dt * sqrt(speed2);
+    const double speed = sqrt(speed2);
+    if (!rate_state) {
+      psi += wj * dt * speed;
+    } else if (speed > 0.0) {
+      const double pss = rs_steady_state(speed, pr + 4);
+      psi = pss + (psi - pss) * exp(-speed * wj * dt / pr[6]);
+    }
   }
   for (int d = 0; d < 3; ++d) {
     st[d] = slip[d];

@@ -11,8 +11,16 @@
 // eta = Zs- Zs+ / (Zs- + Zs+). The total shear traction T = tau0 + tau_lock
 // (tau0 the fault's background traction) is kept when |T| <= tau_S, else
 // scaled to the strength tau_S = C + f(psi) max(0, -(s0 + s^b)), and the slip
-// rate is V = (tau_lock - tau^b) / eta, parallel to T. Friction: linear slip
-// weakening f = mu_s - (mu_s - mu_d) min(psi / D_c, 1), psi the slip path.
+// rate is V = (tau_lock - tau^b) / eta, parallel to T. Friction laws, per face:
+//  * linear slip weakening (the benchmark's law, Sec. 6.2):
+//    f = mu_s - (mu_s - mu_d) min(psi / D_c, 1), psi the slip path;
+//  * rate and state with fast velocity weakening (the Palu run's law):
+//    f(V, psi) = a asinh(V / (2 V0) exp(psi / a)), the fault always slides
+//    with |T| - eta V = f(V, psi) max(0, -(s0 + s^b)) (solved for V by
+//    safeguarded Newton), and over the time the point stands for, h, the
+//    state relaxes at that V: psi <- psi_ss + (psi - psi_ss) exp(-V h / L),
+//    psi_ss(V) = a ln(2 V0 / V sinh(f_ss(V) / a)),
+//    f_ss(V) = f_w + (f0 - (b - a) ln(V / V0) - f_w) / (1 + (V / V_w)^8)^(1/8).
 //
 // Over an element step the traces of both sides come from their stored time
 // derivatives, at the N + 1 Gauss-Legendre points of the step, in order; psi
@@ -29,7 +37,11 @@
 
 namespace seis {
 
-constexpr int kFaultParams = 8;  // s0, tau0 (x, y, z), mu_s, mu_d, D_c, C
+// per face: s0, tau0 (x, y, z), then the law's parameters, the law at [15]:
+//   slip weakening (0): mu_s, mu_d, D_c, C
+//   rate and state (1): a, b, L, V0, f0, f_w, V_w, psi0
+constexpr int kFaultParams = 16;
+constexpr int kLawSlipWeakening = 0, kLawRateState = 1;
 constexpr int kFaultState = 11;  // slip (3), slip path, slip rate (3), shear traction (3), normal stress
 
 struct FaultArgs {

@@ -104,7 +104,7 @@ def load_library(path: str = LIB_PATH):
     lib.seis_points_info.argtypes = [P, C.c_int, C.POINTER(C.c_int64), dp, C.POINTER(C.c_int64)]
     lib.seis_sample.argtypes = [P, C.c_int, C.c_void_p, C.c_void_p]
     lib.seis_set_uplift.argtypes = [P, C.c_int, dp]
-    lib.seis_set_fault.argtypes = [P, C.c_int64, dp]
+    lib.seis_set_fault.argtypes = [P, C.c_int64, C.c_int, dp]
     lib.seis_fault_read.argtypes = [P, dp]
     lib.seis_energy_noalloc.argtypes = [P, C.c_void_p]
     lib.seis_destroy.argtypes = [P]
@@ -199,12 +199,14 @@ class Solver:
         src = np.ascontiguousarray(sources, dtype=np.float64).reshape(-1, 5)
         self._check(self._lib.seis_set_uplift(self._h, src.shape[0], _ptr(src, C.c_double)))
 
-    def set_fault(self, params):
-        """Friction of the fault faces: params [n_fault_faces][8] (or one row for all) =
-        (s0, tau0_x, tau0_y, tau0_z, mu_s, mu_d, D_c, C)."""
+    def set_fault(self, params, law=0):
+        """Friction of the fault faces (one row for all, or one per face):
+        law 0 (slip weakening): (s0, tau0_x, tau0_y, tau0_z, mu_s, mu_d, D_c, C);
+        law 1 (rate and state): (s0, tau0_x, tau0_y, tau0_z, a, b, L, V0, f0, f_w, V_w, psi0)."""
         n = self.info()["n_fault_faces"]
-        p = np.ascontiguousarray(np.broadcast_to(np.asarray(params, dtype=np.float64), (n, 8)))
-        self._check(self._lib.seis_set_fault(self._h, n, _ptr(p, C.c_double)))
+        k = 8 if law == 0 else 12
+        p = np.ascontiguousarray(np.broadcast_to(np.asarray(params, dtype=np.float64), (n, k)))
+        self._check(self._lib.seis_set_fault(self._h, n, int(law), _ptr(p, C.c_double)))
 
     def fault_read(self):
         """Fault state [n_fault_faces][n_face_nodes][14] (see FAULT_POINT_VALUES)."""

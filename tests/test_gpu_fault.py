@@ -204,3 +204,111 @@ def test_graph_replay_and_write_reset():
             s.close()
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
     assert np.abs(out[0][1][..., 3:6]).max() > 0.0
+
+
+# ---------------------------------------------------------------------------
+# rate-and-state friction (fast velocity weakening)
+RS = dict(a=0.01, b=0.014, L=0.2, V0=1e-6, f0=0.6, fw=0.2, Vw=0.1)
+
+
+def rs_psi(tau, sig, V):
+    """State in which background traction tau slides at V against the radiation damping eta V."""
+    p = RS
+    return p["a"] * np.log(2 * p["V0"] / V * np.sinh((tau - RHO * CS / 2.0 * V) / (sig * p["a"])))
+
+
+def rs_params(o):
+    """Per face: s0 = -50 MPa, creeping at 1e-9 m/s under 20 MPa, except a central patch at 31 MPa
+    with the same state (it accelerates)."""
+    p = RS
+    c = o.fault_points.mean(axis=1)
+    mid = 0.5 * (o.geo.xyz.min(axis=0) + o.geo.xyz.max(axis=0))
+    psi0 = rs_psi(20e6, 50e6, 1e-9)
+    P = np.tile([-50e6, 20e6, 0.0, 0.0, p["a"], p["b"], p["L"], p["V0"], p["f0"], p["fw"], p["Vw"], psi0],
+                (c.shape[0], 1))
+    P[np.hypot(c[:, 0] - mid[0], c[:, 1] - mid[1]) < 1000.0, 1] = 31e6
+    return P
+
+
+def rs_oracle(order, steps=4):
+    key = ("rs", order, steps)
+    if key not in _ORACLE:
+        mesh, mats = jittered_box()
+        o = oracle_for(mesh, mats, order)
+        P = rs_params(o)
+        o.set_fault(P, law=1)
+        q = inputs.random_dofs(mesh.n_elements, o.B, seed=order + 50, stress_scale=1e4, velocity_scale=1e4 / 3e6)
+        o.Q[:] = q
+        o.run(steps)
+        _ORACLE[key] = dict(q0=q, Q=o.Q.copy(), fault=fault_table(o), cluster=o.cluster.copy(), params=P)
+    return _ORACLE[key]
+
+
+@pytest.mark.parametrize("precision,kernel", [("fp64", "plain"), ("fp32", "tuned")])
+@pytest.mark.parametrize("order", [4, 6])
+def test_rate_state_against_oracle(order, precision, kernel):
+    from paper_2107_06640_amd import seis
+    ref = rs_oracle(order)
+    say(f"case: rate-and-state fault order={order} {precision}/{kernel} 4 steps")
+    mesh, mats = jittered_box()
+    s = seis.from_mesh(mesh, mats, order, precision=precision, kernel=kernel, mc_min=0)
+    try:
+        s.set_fault(ref["params"], law=1)
+        s.write(ref["q0"])
+        s.run(4)
+        d, _ = s.read()
+        flt = s.fault_read()
+    finally:
+        s.close()
+    fe = field_errors(d, ref["Q"])
+    ee = element_errors(d, ref["Q"])
+    g = match(flt, ref["fault"])
+    r = ref["fault"]
+    errs = {name: np.abs(g[:, cols] - r[:, cols]).max() / max(np.abs(r[:, cols]).max(), 1e-300)
+            for name, cols in (("slip", slice(3, 6)), ("psi", slice(6, 7)), ("rate", slice(7, 10)),
+                               ("traction", slice(10, 13)), ("normal", slice(13, 14)))}
+    fast = np.linalg.norm(r[:, 7:10], axis=1)
+    say(f"  field {fe.max():.2e} element {ee.max():.2e} fault " + " ".join(f"{k} {v:.1e}" for k, v in errs.items())
+        + f" slip rate {fast.min():.2e} .. {fast.max():.2e} m/s")
+    assert fast.max() > 1e3 * fast.min()  # creeping and accelerated points
+    tol = TOL[precision]
+    assert fe.max() <= tol["field"] and ee.max() <= tol["elem"] and max(errs.values()) <= tol["fault"]
+
+
+@pytest.mark.parametrize("precision,kernel", [("fp64", "plain"), ("fp32", "tuned")])
+def test_rate_state_planar_fault_against_ode(precision, kernel):
+    """Planar fault: the slip follows the radiation-damping ODE (DOP853) to 3% after 0.1 s."""
+    from scipy.integrate import solve_ivp
+    from oracle.fault import rs_slip_rate, rs_steady_state
+    from paper_2107_06640_amd import seis
+    p = RS
+    sig, tau0 = 50e6, 30e6
+    psi0 = rs_psi(tau0, sig, 0.3)
+    eta = RHO * CS / 2.0
+
+    def vel(psi):
+        return float(rs_slip_rate(np.array([tau0]), np.array([sig]), eta, np.array([psi]), p["a"], p["V0"])[0])
+
+    def rhs(t, y):
+        V = vel(y[0])
+        pss = float(rs_steady_state(np.array(V), p["a"], p["b"], p["V0"], p["f0"], p["fw"], p["Vw"]))
+        return [-(V / p["L"]) * (y[0] - pss), V]
+
+    sol = solve_ivp(rhs, (0.0, 0.3), [psi0, 0.0], method="DOP853", rtol=1e-10, atol=1e-13, dense_output=True)
+    mesh, mats = inputs.fault_box(2, 2, 6, cell=1000.0, k_fault=3)
+    s = seis.from_mesh(mesh, mats, 4, precision=precision, kernel=kernel, mc_min=0)
+    try:
+        s.set_fault([-sig, tau0, 0.0, 0.0, p["a"], p["b"], p["L"], p["V0"], p["f0"], p["fw"], p["Vw"], psi0], law=1)
+        s.write(np.zeros((mesh.n_elements, s.B, 9)))
+        dt = s.info()["dt_min"]
+        worst, n = 0.0, 0
+        for k in range(1, int(0.3 / dt) + 1):
+            s.step()
+            if k * dt > 0.1 and k % 5 == 0:
+                slip = s.fault_read()[..., 3].mean()
+                worst = max(worst, abs(slip / sol.sol(k * dt)[1] - 1.0))
+                n += 1
+        say(f"case: rate-and-state planar fault {precision}/{kernel}: worst slip error vs ODE {worst:.2e} over {n} samples")
+        assert n > 5 and worst < 0.03
+    finally:
+        s.close()
