@@ -264,16 +264,20 @@ struct Lay {
   static constexpr int PB = BF ? 16 * RT : B;     // extent of a B-row dimension in the image
   static constexpr int PB1 = BF ? 16 * RT1 : B1;  // extent of a B1-row dimension
   // Leading dimensions. BF16: multiples of 4 entries (a fragment reads four
-  // consecutive K entries as one 8-byte word). FP32: padded so that the 64
-  // lanes of a fragment read (16 rows x 4 K entries) fall on distinct LDS
-  // banks up to pairs; a multiple of 8 (or 16 x FT for the lifts, 8- to
-  // 16-way conflicts) is avoided.
-  static constexpr int r4(int x) { return BF ? (x + 3) / 4 * 4 : x + (x % 8 == 0 ? 1 : 0); }
+  // consecutive K entries as one 8-byte word) whose count of 8-byte words is
+  // odd, so that the 16 rows of a fragment read start on 16 distinct bank
+  // pairs (a row stride of 128 bytes put all 16 on one pair). FP32: padded so
+  // that the 64 lanes of a fragment read (16 rows x 4 K entries) fall on
+  // distinct LDS banks up to pairs; a multiple of 8 (or 16 x FT for the lifts,
+  // 8- to 16-way conflicts) is avoided.
+  static constexpr int r4(int x) {
+    return BF ? ((x + 3) / 4 % 2 == 1 ? (x + 3) / 4 * 4 : (x + 3) / 4 * 4 + 4) : x + (x % 8 == 0 ? 1 : 0);
+  }
   static constexpr int ldK = r4(PB1);  // K^d[l < B][m < B1]   (volume: A(k,l) = K[k][l]; FP32 CK: A(m,l) = K[l][m])
   static constexpr int ldT = r4(PB);   // BF16 CK: (K^d)^T[m < B1][l < B]
   // face nodes in slot order (see node_of): FT * 16 slots per face
   static constexpr int ldE = r4(PB);                   // E_f[slot < 16 FT][row < B]
-  static constexpr int ldL = BF ? 16 * FT : 16 * FT + 3;  // L_f[row < B][slot < 16 FT]
+  static constexpr int ldL = BF ? r4(16 * FT) : 16 * FT + 3;  // L_f[row < B][slot < 16 FT]
   static constexpr int nK = 3 * PB * ldK;
   static constexpr int nT = BF ? 3 * PB1 * ldT : 0;
   static constexpr int nE = 4 * 16 * FT * ldE;
@@ -653,11 +657,12 @@ __device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      // rows >= B are the zero padding of the tiled layout: loaded as they are,
-      // so that no load sits behind a lane-dependent branch
+      // a register whose four rows are all >= B (the zero padding of the
+      // tiled layout) is not loaded; the others are loaded whole, so that no
+      // load sits behind a lane-dependent branch
 #pragma unroll
       for (int p = 0; p < 9; ++p)
-        din[t][v][p] = (p >= C0 && p < C1 && carried<AC>(p)) ? qb.ld((t * 4 + v) * 9 + p) : 0.0f;
+        din[t][v][p] = (p >= C0 && p < C1 && carried<AC>(p) && 16 * t + 4 * v < B) ? qb.ld((t * 4 + v) * 9 + p) : 0.0f;
     }
   if (gd) {
 #pragma unroll
@@ -985,7 +990,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
           float x[36];
 #pragma unroll
           for (int r = 0; r < 36; ++r)
-            if (carried<AC>(r % 9)) x[r] = qb.ld(t * 36 + r);  // zero on the padding rows
+            x[r] = (carried<AC>(r % 9) && 16 * t + 4 * (r / 9) < B) ? qb.ld(t * 36 + r) : 0.0f;  // padding rows: 0
 #pragma unroll
           for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -1136,7 +1141,8 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
           for (int u = 0; u < QB; ++u)
 #pragma unroll
             for (int r = 0; r < 36; ++r)
-              if (carried<AC>(r % 9)) q[u][r] = t0 + u < RT ? qb.ld((t0 + u) * 36 + r) : 0.0f;
+              if (carried<AC>(r % 9))
+                q[u][r] = (t0 + u < RT && 16 * (t0 + u) + 4 * (r / 9) < B) ? qb.ld((t0 + u) * 36 + r) : 0.0f;
 #pragma unroll
           for (int u = 0; u < QB; ++u)
 #pragma unroll
@@ -1216,6 +1222,11 @@ __global__ __launch_bounds__(64 * W, (SPLIT >= 2 && N <= 5) ? 2 : 1) void k_corr
           const float* blk0 = inb + s * (4 * 576);  // face s / FT, tile s % FT
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
+            if (16 * (s % FT) + 4 * v >= Bf) {  // all four nodes of the register are padding
+#pragma unroll
+              for (int p = 0; p < 9; ++p) dst[v][p] = 0.0f;
+              continue;
+            }
             const float* blk = blk0 + v * 576;
             const f4 i0 = reinterpret_cast<const f4*>(blk + 8 * lane)[0];
             const f4 i1 = reinterpret_cast<const f4*>(blk + 8 * lane)[1];
@@ -1277,7 +1288,10 @@ __global__ __launch_bounds__(64 * W, (SPLIT >= 2 && N <= 5) ? 2 : 1) void k_corr
           for (int u = 0; u < QB; ++u)
 #pragma unroll
             for (int r = 0; r < 36; ++r)
-              if (carried<AC>(r % 9)) q[u][r] = (u0 + u < MH && t0 + u0 + u < RT) ? qb.ld((t0 + u0 + u) * 36 + r) : 0.0f;
+              if (carried<AC>(r % 9))
+                q[u][r] = (u0 + u < MH && t0 + u0 + u < RT && 16 * (t0 + u0 + u) + 4 * (r / 9) < B)
+                              ? qb.ld((t0 + u0 + u) * 36 + r)
+                              : 0.0f;
 #pragma unroll
           for (int u = 0; u < QB; ++u)
 #pragma unroll
