@@ -34,7 +34,7 @@ PEAK = {  # MI355X published peaks
     "fp32_TF": 157.3,
     "bf16_TF": 2500.0,
 }
-BYTES = {"fp64": 8, "fp32": 4, "bf16": 4}
+BYTES = {"fp64": 8, "fp32": 4, "bf16": 4, "bf16x3": 4}
 
 
 def nb(N):
@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16", "bf16x3"])
     ap.add_argument("--kernel", default="tuned", choices=["tuned", "plain"])
     ap.add_argument("--order", type=int, default=6)
     ap.add_argument("--scale", type=int, default=1)
@@ -366,7 +366,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc"}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16": "bf16-in/f32-acc", "bf16x3": "split-bf16-in (hi+lo, 3 products)/f32-acc"}
 
 
 def workload_description(args, inf):
@@ -469,7 +469,7 @@ def roofline(args, precision, inf, prof):
     flops = cnt["pred_flops" if dom == "predict" else "corr_flops"] * ke / kl
     byts = cnt["pred_bytes" if dom == "predict" else "corr_bytes"] * ke / kl
     avg_s = kms / kl / 1e3
-    peak_tf = PEAK[{"fp64": "fp64_TF", "fp32": "fp32_TF", "bf16": "bf16_TF"}[precision]]
+    peak_tf = PEAK[{"fp64": "fp64_TF", "fp32": "fp32_TF", "bf16": "bf16_TF", "bf16x3": "bf16_TF"}[precision]]
     t_flop = flops / (peak_tf * 1e12)
     t_byte = byts / (PEAK["hbm_GBs"] * 1e9)
     if t_flop >= t_byte:

@@ -69,7 +69,12 @@ enum {
                               vertex ids; see seis_set_fault. Its two elements share an LTS cluster. */
 };
 
-enum { SEIS_FP64 = 0, SEIS_FP32 = 1, SEIS_BF16 = 2 };
+/* Precision of the element update's operands. SEIS_BF16_SPLIT: every operand
+ * of a matrix-core product is split into two BF16 numbers, x = hi + lo with
+ * hi = bf16(x) and lo = bf16(x - hi), and each product is formed from three
+ * BF16 products (hi hi + hi lo + lo hi) with FP32 accumulation: about 16
+ * significant bits per operand, near FP32 accuracy on the BF16 matrix cores. */
+enum { SEIS_FP64 = 0, SEIS_FP32 = 1, SEIS_BF16 = 2, SEIS_BF16_SPLIT = 3 };
 enum { SEIS_KERNEL_TUNED = 0, SEIS_KERNEL_PLAIN = 1 };
 
 typedef struct seis_t seis_t; /* opaque; owns all device memory */
@@ -93,7 +98,7 @@ typedef struct {
 } seis_materials_t;
 
 typedef struct {
-  int precision;    /* SEIS_FP64 / SEIS_FP32 / SEIS_BF16 (operands; FP32 accumulation) */
+  int precision;    /* SEIS_FP64 / SEIS_FP32 / SEIS_BF16 / SEIS_BF16_SPLIT (operands; FP32 accumulation) */
   int kernel;       /* SEIS_KERNEL_TUNED (default) or SEIS_KERNEL_PLAIN */
   double cfl;       /* C in dt_K = C/(2N+1) h_K / c_p,K (Sec. 4.4); default 0.35 */
   double g;         /* gravitational acceleration (Sec. 3); default 9.81 */

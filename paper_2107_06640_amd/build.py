@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libseis.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["refelem.cpp", "setup.cpp", "assemble.hip", "abi.hip", "kernels_plain.hip", "tuned.hip", "tuned_f32.hip",
-           "tuned_bf16.hip", "fno.hip", "energy.hip", "probe.hip", "forcing.hip",
+           "tuned_bf16.hip", "tuned_bf16x3.hip", "fno.hip", "energy.hip", "probe.hip", "forcing.hip",
            "fault.hip"]
 
 FLAGS = [

@@ -529,9 +529,11 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
   seis_options_t o;
   seis_default_options(&o);
   if (opt) o = *opt;
-  if (o.precision < SEIS_FP64 || o.precision > SEIS_BF16) return setup_fail(SEIS_EINVAL, "bad precision");
+  if (o.precision < SEIS_FP64 || o.precision > SEIS_BF16_SPLIT) return setup_fail(SEIS_EINVAL, "bad precision");
   if (o.kernel != SEIS_KERNEL_TUNED && o.kernel != SEIS_KERNEL_PLAIN) return setup_fail(SEIS_EINVAL, "bad kernel");
-  if (o.kernel == SEIS_KERNEL_PLAIN && o.precision == SEIS_BF16)
+  if (o.precision == SEIS_BF16_SPLIT && order > 6)
+    return setup_fail(SEIS_EINVAL, "split BF16 supports orders 3..6 (its two LDS images of order 7 exceed a CU)");
+  if (o.kernel == SEIS_KERNEL_PLAIN && (o.precision == SEIS_BF16 || o.precision == SEIS_BF16_SPLIT))
     return setup_fail(SEIS_EINVAL, "BF16 operands need the tuned (MFMA) kernels");
   if (order < 3 || order > 7) return setup_fail(SEIS_EINVAL, "order must be in 3..7");
   if (o.mc_min < 0) return setup_fail(SEIS_EINVAL, "mc_min must be >= 0");

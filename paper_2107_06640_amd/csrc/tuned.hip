@@ -158,6 +158,21 @@ std::vector<double> ref_image_n(const Model& M, int& bytes) {
 
 }  // namespace
 
+// matrix-core launches by precision: 1 FP32, 2 BF16, 3 split BF16
+hipError_t pred_dispatch_any(int precision, int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1,
+                             const Sched& sc, hipStream_t s) {
+  if (precision == 1) return pred_dispatch_f32(N, c, a, e0, e1, sc, s);
+  if (precision == 3) return pred_dispatch_bf16x3(N, c, a, e0, e1, sc, s);
+  return pred_dispatch_bf16(N, c, a, e0, e1, sc, s);
+}
+
+hipError_t corr_dispatch_any(int precision, int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1,
+                             hipStream_t s) {
+  if (precision == 1) return corr_dispatch_f32(N, c, a, e0, e1, s);
+  if (precision == 3) return corr_dispatch_bf16x3(N, c, a, e0, e1, s);
+  return corr_dispatch_bf16(N, c, a, e0, e1, s);
+}
+
 hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevData<double>& d64,
                        const DevData<float>& d32, int tile, int acoustic, std::vector<void*>& owned,
                        int64_t& bytes) {
@@ -262,9 +277,22 @@ hipError_t tuned_build(TunedData& t, const Model& M, int precision, const DevDat
     st = upload(owned, bytes, &r, ref);
     a.ref = r;
   } else {
-    std::vector<double> ref = ref_image_n<OpBF16>(M, lbytes);
+    // BF16: one image rounded to BF16; split BF16 (precision 3): the image of
+    // hi = bf16(x), then the image of lo = bf16(x - hi)
+    const bool split = precision == 3;
+    std::vector<double> ref = split ? ref_image_n<OpBF16X3>(M, lbytes) : ref_image_n<OpBF16>(M, lbytes);
     std::vector<unsigned short> rb(lbytes / 2, 0);
-    for (size_t i = 0; i < ref.size() && i < rb.size(); ++i) rb[i] = f2bf((float)ref[i]);
+    const size_t one = split ? rb.size() / 2 : rb.size();
+    for (size_t i = 0; i < ref.size() && i < one; ++i) {
+      const float x = (float)ref[i];
+      rb[i] = f2bf(x);
+      if (split) {
+        const uint32_t u = uint32_t(rb[i]) << 16;
+        float hi;
+        std::memcpy(&hi, &u, 4);
+        rb[one + i] = f2bf(x - hi);
+      }
+    }
     unsigned short* r;
     st = upload(owned, bytes, &r, rb);
     a.ref = r;
@@ -279,8 +307,7 @@ hipError_t tuned_predict(const TunedData& t, int precision, int N, int c0, int c
                          const Sched& sc, hipStream_t s) {
   if (precision == 0) return launch_predict_plain<double>(N, t.d64, e0, e1 - e0, sc, s);
   if (e1 - e0 < t.mc_min) return launch_predict_plain<float>(N, t.d32, e0, e1 - e0, sc, s);
-  hipError_t st = precision == 1 ? pred_dispatch_f32(N, t.pc, t.a, e0, e1, sc, s)
-                                 : pred_dispatch_bf16(N, t.pc, t.a, e0, e1, sc, s);
+  hipError_t st = pred_dispatch_any(precision, N, t.pc, t.a, e0, e1, sc, s);
   if (st != hipSuccess) return st;
   const int64_t f0 = t.fix_start[c0], nf = t.fix_start[c1 + 1] - f0;
   return fixup_dispatch(N, t.a, t.a.fix_list + f0, nf, s);
@@ -305,8 +332,7 @@ hipError_t tuned_correct(const TunedData& t, int precision, int N, int c0, int c
     if (st != hipSuccess) return st;
     c = c2 + 1;
   }
-  return precision == 1 ? corr_dispatch_f32(N, t.cc, t.a, e0, e1, s)
-                        : corr_dispatch_bf16(N, t.cc, t.a, e0, e1, s);
+  return corr_dispatch_any(precision, N, t.cc, t.a, e0, e1, s);
 }
 
 
@@ -447,16 +473,13 @@ hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s) {
       for (int rm : {0, 1}) {
         const LaunchCfg c{w, cap, rm, 2, 0};
         float ms = 0.0f;
-        // predictor: both shapes of the precision (see LaunchCfg::variant)
-        for (int var = 0; var < 2 && cap <= 2; ++var) {
+        // predictor: both shapes of the precision (see LaunchCfg::variant;
+        // split BF16 has one)
+        for (int var = 0; var < (t.precision == 3 ? 1 : 2) && cap <= 2; ++var) {
           LaunchCfg cv = c;
           cv.variant = var;
           hipError_t st = time_launch(
-              [&]() {
-                return t.precision == 1 ? pred_dispatch_f32(t.N, cv, t.a, e0, ei, Sched{}, s)
-                                        : pred_dispatch_bf16(t.N, cv, t.a, e0, ei, Sched{}, s);
-              },
-              s, reps, ms);
+              [&]() { return pred_dispatch_any(t.precision, t.N, cv, t.a, e0, ei, Sched{}, s); }, s, reps, ms);
           if (st != hipSuccess) return st;
           if (ms < tp) {
             tp = ms;
@@ -467,11 +490,7 @@ hipError_t tuned_autotune(TunedData& t, const Model& M, hipStream_t s) {
           LaunchCfg cs = c;
           cs.split = sp;
           hipError_t st = time_launch(
-              [&]() {
-                return t.precision == 1 ? corr_dispatch_f32(t.N, cs, t.a, e0, ei, s)
-                                        : corr_dispatch_bf16(t.N, cs, t.a, e0, ei, s);
-              },
-              s, reps, ms);
+              [&]() { return corr_dispatch_any(t.precision, t.N, cs, t.a, e0, ei, s); }, s, reps, ms);
           if (st != hipSuccess) return st;
           if (ms < tc) {
             tc = ms;

@@ -70,6 +70,9 @@ hipError_t pred_dispatch_bf16(int N, const LaunchCfg& c, const TArgs& a, int64_t
                               hipStream_t s);
 hipError_t corr_dispatch_f32(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s);
 hipError_t corr_dispatch_bf16(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s);
+hipError_t pred_dispatch_bf16x3(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, const Sched& sc,
+                                hipStream_t s);
+hipError_t corr_dispatch_bf16x3(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, int64_t e1, hipStream_t s);
 
 // acoustic: nonzero runs 16-element groups of acoustic elements in the
 // 4-quantity form.

@@ -61,8 +61,11 @@ struct OpF32 {};    // FP32 operands, I~ parked in LDS as far as it fits
 struct OpF32H {};   // FP32 operands, I~ parked in HBM only (the LDS keeps the reference block)
 struct OpBF16 {};   // BF16 operands, 16x16x16 products (K = one row tile)
 struct OpBF16W {};  // BF16 operands, 16x16x32 products (K = two row tiles)
+struct OpBF16X3 {}; // split BF16 operands: x = hi + lo, three 16x16x16 products hi hi + hi lo + lo hi
 template <class Op>
-constexpr bool is_bf = std::is_same<Op, OpBF16>::value || std::is_same<Op, OpBF16W>::value;
+constexpr bool split3 = std::is_same<Op, OpBF16X3>::value;
+template <class Op>
+constexpr bool is_bf = std::is_same<Op, OpBF16>::value || std::is_same<Op, OpBF16W>::value || split3<Op>;
 template <class Op>
 constexpr bool wide_k = std::is_same<Op, OpBF16W>::value;
 template <class Op>
@@ -103,6 +106,27 @@ __device__ __forceinline__ f4 mfma_k32(s4 a0, s4 a1, s4 b0, s4 b1, f4 c) {
 __device__ __forceinline__ s4 pack4(float a, float b, float c, float d) {
   typedef unsigned u2 __attribute__((ext_vector_type(2)));
   return __builtin_bit_cast(s4, u2{pack2(a, b), pack2(c, d)});
+}
+
+// Split BF16 operands (OpBF16X3): x = hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi) (x - hi is exact in FP32), so that a product of two split
+// operands, hi hi + hi lo + lo hi, keeps about 16 significant bits of each
+// (the lo lo term is below FP32 accumulation round-off).
+__device__ __forceinline__ float bf_value(short h) { return __uint_as_float((unsigned)(unsigned short)h << 16); }
+
+__device__ __forceinline__ void split4(float a, float b, float c, float d, s4& hi, s4& lo) {
+  hi = pack4(a, b, c, d);
+  lo = pack4(a - bf_value(hi[0]), b - bf_value(hi[1]), c - bf_value(hi[2]), d - bf_value(hi[3]));
+}
+
+// acc += A B on the BF16 matrix cores: one product, or three for split operands
+template <class Op>
+__device__ __forceinline__ f4 mfma_bf(s4 ah, s4 al, s4 bh, s4 bl, f4 acc) {
+  if constexpr (split3<Op>) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
 }
 
 // (A_e u)_p for e = x, y, z: the three Jacobians of the velocity-stress
@@ -286,10 +310,15 @@ struct Lay {
   static constexpr int tail = 16 * (maxld > ldT ? maxld : ldT) + 64;
   // the lift block starts on a 16-byte boundary (the corrector stages it alone)
   static constexpr int oK = 0, oT = nK, oE = nK + nT, oL = (oE + nE + 7) / 8 * 8;
-  static constexpr int total = oL + nL + tail;
-  static constexpr int bytes = (total * (BF ? 2 : 4) + 15) / 16 * 16;
-  // the corrector stages only the lifts and the tail: [oL, total)
-  static constexpr int lift_bytes = ((nL + tail) * (BF ? 2 : 4) + 15) / 16 * 16;
+  // one image (a multiple of 16 bytes); split BF16 keeps the hi image and
+  // then the lo image
+  static constexpr int esz = BF ? 2 : 4;
+  static constexpr int images = split3<Op> ? 2 : 1;
+  static constexpr int total = ((oL + nL + tail) * esz + 15) / 16 * 16 / esz;
+  static constexpr int bytes = images * total * esz;
+  // the corrector stages only the lifts and the tail, [oL, total), of each image
+  static constexpr int lift_elems = ((nL + tail) * esz + 15) / 16 * 16 / esz;
+  static constexpr int lift_bytes = images * lift_elems * esz;
 };
 
 // A zero the compiler cannot see through. Views built with it are re-read
@@ -320,17 +349,22 @@ struct GroupBuf {
   }
 };
 
-// A(i, k) = R[i * LD + k] (row-major) or R[k * LD + i] (transposed store)
+// A(i, k) = R[i * LD + k] (row-major) or R[k * LD + i] (transposed store);
+// for split BF16 the lo part of the same entry sits lo entries further on
 template <class R, int LD, bool TR>
 struct View {
   const R* p;
   int o;
-  __device__ __forceinline__ View(const R* base) : p(base), o(opaque_zero()) {}
+  int lo;
+  __device__ __forceinline__ View(const R* base, int lo_off = 0) : p(base), o(opaque_zero()), lo(lo_off) {}
   __device__ __forceinline__ R at(int i, int k) const { return TR ? p[o + k * LD + i] : p[o + i * LD + k]; }
-  // four consecutive K entries k0..k0+3 (BF16, row-major only)
+  // four consecutive K entries k0..k0+3 (BF16, row-major only), and their lo parts
   __device__ __forceinline__ s4 at4(int i, int k0) const {
     static_assert(!TR, "four-entry reads need the row-major store");
     return *reinterpret_cast<const s4*>(p + o + i * LD + k0);
+  }
+  __device__ __forceinline__ s4 at4_lo(int i, int k0) const {
+    return *reinterpret_cast<const s4*>(p + o + lo + i * LD + k0);
   }
 };
 
@@ -427,9 +461,13 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
   } else {
     float bv[2][4][9];
     s4 an[2][MT];  // A fragments of this row tile and the next
+    s4 al[2][MT];  // their lo parts (split BF16)
     auto load_a = [&](int t, s4(&dst)[MT]) {
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) dst[mt] = A.at4(16 * mt + el, 16 * t + 4 * g);
+      for (int mt = 0; mt < MT; ++mt) {
+        dst[mt] = A.at4(16 * mt + el, 16 * t + 4 * g);
+        if constexpr (split3<Op>) al[t & 1][mt] = A.at4_lo(16 * mt + el, 16 * t + 4 * g);
+      }
     };
     if constexpr (PIPE) {
 #pragma unroll
@@ -451,16 +489,22 @@ __device__ __forceinline__ void contract_fn(f4 (&acc)[MT][9], const V& A, int nr
         for (int v = 0; v < 4; ++v) rowfn(t, v, cur[v]);
         load_a(t, an[t & 1]);
       }
-      s4 b[9];
+      s4 b[9], bl[9];
 #pragma unroll
-      for (int p = 0; p < 9; ++p)
-        if (carried<AC>(p)) b[p] = pack4(cur[0][p], cur[1][p], cur[2][p], cur[3][p]);
+      for (int p = 0; p < 9; ++p) {
+        if (!carried<AC>(p)) continue;
+        if constexpr (split3<Op>)
+          split4(cur[0][p], cur[1][p], cur[2][p], cur[3][p], b[p], bl[p]);
+        else
+          b[p] = pack4(cur[0][p], cur[1][p], cur[2][p], cur[3][p]);
+      }
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const s4 a = an[t & 1][mt];
+        const s4 alo = split3<Op> ? al[t & 1][mt] : a;
 #pragma unroll
         for (int p = 0; p < 9; ++p)
-          if (carried<AC>(p)) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], acc[mt][p], 0, 0, 0);
+          if (carried<AC>(p)) acc[mt][p] = mfma_bf<Op>(a, alo, b[p], split3<Op> ? bl[p] : b[p], acc[mt][p]);
       }
       if constexpr (PIPE) __builtin_amdgcn_sched_barrier(0);
     }
@@ -577,7 +621,7 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     {
-      const View<unsigned short, L::ldT, false> A(lds + L::oT + d * L::PB1 * L::ldT);  // (K^d)^T[m][l]
+      const View<unsigned short, L::ldT, false> A(lds + L::oT + d * L::PB1 * L::ldT, L::total);  // (K^d)^T[m][l]
       if constexpr (wide_k<Op>) {
         // two input row tiles per 16x16x32 product
 #pragma unroll
@@ -616,17 +660,23 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
         float z[4][9];
 #pragma unroll
         for (int v = 0; v < 4; ++v) star_q<AC>(G[3 * d], G[3 * d + 1], G[3 * d + 2], lam, mu, rinv, din[t][v], z[v]);
-        s4 bz[NP];
+        s4 bz[NP], bzl[NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
-          if (carried<AC>(P0 + p)) bz[p] = pack4(z[0][P0 + p], z[1][P0 + p], z[2][P0 + p], z[3][P0 + p]);
+        for (int p = 0; p < NP; ++p) {
+          if (!carried<AC>(P0 + p)) continue;
+          if constexpr (split3<Op>)
+            split4(z[0][P0 + p], z[1][P0 + p], z[2][P0 + p], z[3][P0 + p], bz[p], bzl[p]);
+          else
+            bz[p] = pack4(z[0][P0 + p], z[1][P0 + p], z[2][P0 + p], z[3][P0 + p]);
+        }
         const int k0 = 16 * t + 4 * g;
 #pragma unroll
         for (int mt = 0; mt < RTO; ++mt) {
           const s4 af = A.at4(16 * mt + el, k0);
+          const s4 afl = split3<Op> ? A.at4_lo(16 * mt + el, k0) : af;
 #pragma unroll
           for (int p = 0; p < NP; ++p)
-            if (carried<AC>(P0 + p)) acc[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bz[p], acc[mt][p], 0, 0, 0);
+            if (carried<AC>(P0 + p)) acc[mt][p] = mfma_bf<Op>(af, afl, bz[p], split3<Op> ? bzl[p] : bz[p], acc[mt][p]);
         }
       }
     }
@@ -745,8 +795,8 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
   using L = Lay<Op, N>;
   constexpr int B = L::B, B1 = L::B1, RT = L::RT, RT1 = L::RT1;
   using R = RefT<Op>;
-  const View<R, L::ldK, false> A0(lds + L::oK), A1(lds + L::oK + L::PB * L::ldK),
-      A2(lds + L::oK + 2 * L::PB * L::ldK);
+  const View<R, L::ldK, false> A0(lds + L::oK, L::total), A1(lds + L::oK + L::PB * L::ldK, L::total),
+      A2(lds + L::oK + 2 * L::PB * L::ldK, L::total);
   if constexpr (!is_bf<Op>) {
     constexpr int D = kPrefetch;
     float xb[D + 1][9];
@@ -876,17 +926,23 @@ __device__ __forceinline__ void volume(f4 (&dq)[row_tiles(nbasis(N))][9], const 
           for (int p = 0; p < 9; ++p)
             if (carried<AC>(p)) z[v][p] = ok ? z[v][p] : 0.0f;
         }
-        s4 b[9];
+        s4 b[9], bl[9];
 #pragma unroll
-        for (int p = 0; p < 9; ++p)
-          if (carried<AC>(p)) b[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
+        for (int p = 0; p < 9; ++p) {
+          if (!carried<AC>(p)) continue;
+          if constexpr (split3<Op>)
+            split4(z[0][p], z[1][p], z[2][p], z[3][p], b[p], bl[p]);
+          else
+            b[p] = pack4(z[0][p], z[1][p], z[2][p], z[3][p]);
+        }
         const View<R, L::ldK, false>& A = d == 0 ? A0 : (d == 1 ? A1 : A2);
 #pragma unroll
         for (int mt = 0; mt < RT; ++mt) {
           const s4 a = A.at4(16 * mt + el, k0);
+          const s4 alo = split3<Op> ? A.at4_lo(16 * mt + el, k0) : a;
 #pragma unroll
           for (int p = 0; p < 9; ++p)
-            if (carried<AC>(p)) dq[mt][p] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[p], dq[mt][p], 0, 0, 0);
+            if (carried<AC>(p)) dq[mt][p] = mfma_bf<Op>(a, alo, b[p], split3<Op> ? bl[p] : b[p], dq[mt][p]);
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -925,7 +981,8 @@ struct PredLds {
   static constexpr int slice = L::RT * 36 * 64;  // BF16 values per wavefront
   static constexpr int perm_bytes = (6 * L::Bf * 4 + 15) / 16 * 16;
   static constexpr int budget = 160 * 1024 - L::bytes - perm_bytes;
-  static constexpr bool park_lds = L::BF && W * slice * 2 <= budget;
+  // split BF16 keeps I~ in FP32 (in HBM: its two images leave no room in LDS)
+  static constexpr bool park_lds = L::BF && !split3<Op> && W * slice * 2 <= budget;
   static constexpr int f32_fit = budget / (W * 36 * 64 * 4);
   static constexpr int f32_tiles =
       (L::BF || hbm_park<Op>) ? 0 : (f32_fit < L::RT ? (f32_fit > 0 ? f32_fit : 0) : L::RT);
@@ -1049,7 +1106,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
 #pragma unroll
           for (int p = 0; p < 9; ++p)
             if (carried<AC>(p)) va[t][p] = f4{0.f, 0.f, 0.f, 0.f};
-        const View<R, L::ldE, false> AE(lds + L::oE + f * 16 * FT * L::ldE);
+        const View<R, L::ldE, false> AE(lds + L::oE + f * 16 * FT * L::ldE, L::total);
         contract_fn<Op, View<R, L::ldE, false>, RT, FT, true, false, AC>(va, AE, B, el, g, itil_at(Ig));
         float V[FT][4][9];
 #pragma unroll
@@ -1112,7 +1169,7 @@ __global__ __launch_bounds__(64 * W) void k_predict_tuned(TArgs a, int64_t e0, i
             for (int p = 0; p < 9; ++p)
               if (carried<AC>(p)) V[t][v][p] = out[p];
           }
-        const View<R, L::ldL, false> AL(lds + L::oL + f * L::PB * L::ldL);
+        const View<R, L::ldL, false> AL(lds + L::oL + f * L::PB * L::ldL, L::total);
         contract_fn<Op, View<R, L::ldL, false>, FT, RT, false, true, AC>(dq, AL, Bf, el, g,
                                                             [&](int t, int v, float (&b)[9]) {
 #pragma unroll
@@ -1189,7 +1246,10 @@ __global__ __launch_bounds__(64 * W, (SPLIT >= 2 && N <= 5) ? 2 : 1) void k_corr
   // only the lifts (and the tail their reads may run into) are staged: ldsL
   // holds the block from offset oL on
   const R* ldsL = reinterpret_cast<const R*>(lds_raw);
-  stage_ref<Op>(lds_raw, reinterpret_cast<const R*>(a.ref) + L::oL, L::lift_bytes, 64 * W);
+  stage_ref<Op>(lds_raw, reinterpret_cast<const R*>(a.ref) + L::oL, L::lift_elems * L::esz, 64 * W);
+  if constexpr (split3<Op>)  // the lo image's lifts after the hi image's
+    stage_ref<Op>(lds_raw + L::lift_elems * L::esz, reinterpret_cast<const R*>(a.ref) + L::total + L::oL,
+                  L::lift_elems * L::esz, 64 * W);
   __syncthreads();
   // the wavefront index is uniform across the wavefront: keep it (and every
   // group base and buffer descriptor derived from it) in scalar registers
@@ -1266,7 +1326,7 @@ __global__ __launch_bounds__(64 * W, (SPLIT >= 2 && N <= 5) ? 2 : 1) void k_corr
             for (int p = 0; p < 9; ++p)
               if (carried<AC>(p)) V[v][p] = ok ? out[p] : 0.0f;
           }
-          const View<R, L::ldL, false> AL(ldsL + f * L::PB * L::ldL + t0 * 16 * L::ldL + 16 * t);
+          const View<R, L::ldL, false> AL(ldsL + f * L::PB * L::ldL + t0 * 16 * L::ldL + 16 * t, L::lift_elems);
           contract_fn<Op, View<R, L::ldL, false>, 1, MH, false, true, AC>(dq, AL, Bf - 16 * t < 16 ? Bf - 16 * t : 16, el,
                                                                       g, [&](int, int v, float (&b)[9]) {
 #pragma unroll
@@ -1379,8 +1439,15 @@ hipError_t pred_dispatch(int N, const LaunchCfg& c, const TArgs& a, int64_t e0, 
   if constexpr (std::is_same<Op, OpBF16>::value)
     if (c.variant == 1) return pred_dispatch<OpBF16W>(N, c, a, e0, e1, sc, s);
   const int W = c.waves;
-#define SEIS_P(NN, WW) \
-  if (N == NN && W == WW) return launch_pred<Op, NN, WW>(a, e0, e1, sc, c, s);
+  // a shape whose LDS block does not fit a CU (split BF16 at order 7: two
+  // images) is not compiled; the set-up rejects that combination
+#define SEIS_P(NN, WW)                                                          \
+  if (N == NN && W == WW) {                                                     \
+    if constexpr (PredLds<Op, NN, WW>::bytes <= 160 * 1024)                     \
+      return launch_pred<Op, NN, WW>(a, e0, e1, sc, c, s);                      \
+    else                                                                        \
+      return hipErrorInvalidValue;                                              \
+  }
   SEIS_P(2, 2) SEIS_P(2, 4)
   SEIS_P(3, 2) SEIS_P(3, 4)
   SEIS_P(4, 2) SEIS_P(4, 4)

@@ -14,9 +14,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("SEIS_LIB", os.path.join(_HERE, "libseis.so"))
 
-SEIS_FP64, SEIS_FP32, SEIS_BF16 = 0, 1, 2
+SEIS_FP64, SEIS_FP32, SEIS_BF16, SEIS_BF16_SPLIT = 0, 1, 2, 3
 SEIS_KERNEL_TUNED, SEIS_KERNEL_PLAIN = 0, 1
-PRECISIONS = {"fp64": SEIS_FP64, "fp32": SEIS_FP32, "bf16": SEIS_BF16}
+# "bf16x3": split BF16 operands (hi + lo), three BF16 products per product
+PRECISIONS = {"fp64": SEIS_FP64, "fp32": SEIS_FP32, "bf16": SEIS_BF16, "bf16x3": SEIS_BF16_SPLIT}
 KERNELS = {"tuned": SEIS_KERNEL_TUNED, "plain": SEIS_KERNEL_PLAIN}
 ERRORS = {-1: "SEIS_EINVAL", -2: "SEIS_ENOMEM", -3: "SEIS_EDEVICE", -4: "SEIS_EORDER", -5: "SEIS_ERANGE"}
 

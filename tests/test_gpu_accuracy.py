@@ -27,6 +27,9 @@ Findings the assertions encode:
 * BF16 operands (8 significant bits) leave errors of about 1e-2, above the
   FP64 discretisation error from order 4 on; the bound below (5e-2) only
   guards against regressions.
+* Split BF16 operands (hi + lo, three BF16 products per product, orders 3-6)
+  keep about 17 significant bits per operand (|x - hi - lo| <= 2^-18 |x|):
+  within the larger of the FP64 discretisation error and a 5e-5 floor.
 """
 import math
 import sys
@@ -43,6 +46,7 @@ pytestmark = pytest.mark.gpu
 ROCK = inputs.lame(2700.0, 6000.0, 3464.0)
 FIELDS = ["sxx", "syy", "szz", "sxy", "syz", "sxz", "vx", "vy", "vz"]
 FP32_FLOOR = 2e-6
+SPLIT_FLOOR = 5e-5
 BF16_BOUND = 5e-2
 
 
@@ -93,30 +97,32 @@ def study(name, mesh, mats, order, steps, fn, cfl, g=9.81, eta_fn=None, norm_tim
         pts = o.eta_points()
         eta0 = eta_fn(pts.reshape(-1, 3), 0.0).reshape(pts.shape[:2])
     out = {}
-    for prec, kern in (("fp64", "plain"), ("fp32", "tuned"), ("bf16", "tuned")):
+    precs = [("fp64", "plain"), ("fp32", "tuned"), ("bf16", "tuned")] + ([("bf16x3", "tuned")] if order <= 6 else [])
+    for prec, kern in precs:
         out[prec] = run(mesh, mats, order, steps, q0, eta0, prec, kern, cfl, g)
     t = out["fp64"][2]
     err64, _ = l2_fields(o, out["fp64"][0], fn, t)
     nrm = np.max([group_norm(l2_fields(o, np.zeros_like(q0), fn, tn)[1]) for tn in norm_times], axis=0)
     disc = err64 / nrm
     row = {"case": name, "order": order, "steps": steps, "t": t, "fp64_vs_exact": disc}
-    for prec in ("fp32", "bf16"):
+    reduced = [p for p, _ in precs if p != "fp64"]
+    for prec in reduced:
         diff, _ = l2_fields(o, out[prec][0] - out["fp64"][0], lambda x, tt: np.zeros((x.shape[0], 9)), t)
         row[prec + "_vs_fp64"] = diff / nrm
     if eta_fn is not None:
         ex = eta_fn(pts.reshape(-1, 3), t).reshape(pts.shape[:2])
         sc = np.abs(eta0).max()
-        row["eta"] = {"fp64_vs_exact": np.abs(out["fp64"][1] - ex).max() / sc,
-                      "fp32_vs_fp64": np.abs(out["fp32"][1] - out["fp64"][1]).max() / sc,
-                      "bf16_vs_fp64": np.abs(out["bf16"][1] - out["fp64"][1]).max() / sc}
+        row["eta"] = {"fp64_vs_exact": np.abs(out["fp64"][1] - ex).max() / sc}
+        for prec in reduced:
+            row["eta"][prec + "_vs_fp64"] = np.abs(out[prec][1] - out["fp64"][1]).max() / sc
     CASES.append(row)
     fmt = lambda v: " ".join(f"{x:.1e}" for x in v)
     say(f"| {name} | {order} | fp64-exact {fmt(disc)} |")
-    say(f"|   | | fp32-fp64  {fmt(row['fp32_vs_fp64'])} |")
-    say(f"|   | | bf16-fp64  {fmt(row['bf16_vs_fp64'])} |")
+    for prec in reduced:
+        say(f"|   | | {prec}-fp64 {fmt(row[prec + '_vs_fp64'])} |")
     if eta_fn is not None:
-        say(f"|   | | eta: fp64-exact {row['eta']['fp64_vs_exact']:.1e} fp32-fp64 {row['eta']['fp32_vs_fp64']:.1e} "
-            f"bf16-fp64 {row['eta']['bf16_vs_fp64']:.1e} |")
+        say(f"|   | | eta: fp64-exact {row['eta']['fp64_vs_exact']:.1e} "
+            + " ".join(f"{p}-fp64 {row['eta'][p + '_vs_fp64']:.1e}" for p in reduced) + " |")
     return row
 
 
@@ -133,6 +139,8 @@ def test_plane_wave_precision_within_discretisation_error(order):
     assert np.all(row["fp64_vs_exact"][live] < 0.1)
     assert np.all(row["fp32_vs_fp64"][live] <= np.maximum(row["fp64_vs_exact"][live], FP32_FLOOR))
     assert np.all(row["bf16_vs_fp64"][live] <= BF16_BOUND)
+    if "bf16x3_vs_fp64" in row:
+        assert np.all(row["bf16x3_vs_fp64"][live] <= np.maximum(row["fp64_vs_exact"][live], SPLIT_FLOOR))
 
 
 @pytest.mark.parametrize("order", [3, 4, 5, 6, 7])
@@ -150,3 +158,6 @@ def test_standing_wave_precision_within_discretisation_error(order):
     assert np.all(row["fp32_vs_fp64"][live] <= np.maximum(row["fp64_vs_exact"][live], FP32_FLOOR))
     assert row["eta"]["fp32_vs_fp64"] <= max(row["eta"]["fp64_vs_exact"], FP32_FLOOR)
     assert np.all(row["bf16_vs_fp64"][live] <= BF16_BOUND) and row["eta"]["bf16_vs_fp64"] <= BF16_BOUND
+    if "bf16x3_vs_fp64" in row:
+        assert np.all(row["bf16x3_vs_fp64"][live] <= np.maximum(row["fp64_vs_exact"][live], SPLIT_FLOOR))
+        assert row["eta"]["bf16x3_vs_fp64"] <= max(row["eta"]["fp64_vs_exact"], SPLIT_FLOOR)
