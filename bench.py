@@ -1,6 +1,6 @@
 """Throughput of the ADER-DG element update on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp64|bf16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp64|bf16|bf16x3]
                     [--kernel tuned|plain] [--order 6] [--scale 1] [--no-cpu-baseline]
 
 Workload: the graded, jittered ocean-over-solid box (72 x 72 x 64 cubes x 6 =
@@ -12,7 +12,8 @@ Inputs (mesh data, DOFs) are resident in HBM before the timed region.
 
 Prints one JSON line with the metric, a roofline object for the dominant
 kernel (event-timed on the library's stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+bounded sample of the same workload. An FP32 run adds the same measurement
+with BF16 operands ("bf16") and with split BF16 operands ("bf16x3").
 """
 from __future__ import annotations
 
@@ -155,7 +156,7 @@ def tiled_dofs(E, B, seed, wet):
 
 
 def precision_sweep(args):
-    """Per-field error of FP32 and BF16 against FP64, and throughput, at orders 4-7.
+    """Per-field error of FP32, split BF16 and BF16 against FP64, and throughput, at orders 4-7.
 
     The benchmark mesh, 504 sub-steps of dt_min (63 macro steps of 8), from
     seeded Gaussian v_z pulses at the seafloor. The FP64 reference is the
@@ -198,7 +199,7 @@ def precision_sweep(args):
         nrm = np.sqrt(np.einsum("e,ebp->p", w, ref ** 2))
         print(json.dumps({"order": order, "precision": "fp64", "kernel": "plain", "substeps": sub,
                           "updates_per_s": ups}), flush=True)
-        for prec in ("fp32", "bf16"):
+        for prec in ("fp32", "bf16x3", "bf16") if order <= 6 else ("fp32", "bf16"):
             d, eta, ups, _ = run(order, prec, "tuned", q)
             err = np.sqrt(np.einsum("e,ebp->p", w, (d - ref) ** 2))
             rel = err / np.where(nrm > 0, nrm, nrm.max())
@@ -284,9 +285,9 @@ def main():
                     help="acoustic elements in the nine-quantity embedding everywhere (no 4-quantity groups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true",
-                    help="FP32 runs: skip the BF16-operand measurement reported beside the FP32 line")
+                    help="FP32 runs: skip the BF16 and split-BF16 measurements reported beside the FP32 line")
     ap.add_argument("--sweep", action="store_true",
-                    help="precision sweep: FP32/BF16 against FP64 at orders 4-7 (one JSON line each)")
+                    help="precision sweep: FP32/split BF16/BF16 against FP64 at orders 4-7 (one JSON line each)")
     ap.add_argument("--sweep-orders", type=int, nargs="+", default=[4, 5, 6, 7])
     ap.add_argument("--sweep-steps", type=int, default=63, help="macro steps (63 x 8 = 504 sub-steps)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
@@ -350,17 +351,19 @@ def main():
         "kernels_ms": {k: v[0] for k, v in prof.items()},
     }
     if args.precision == "fp32" and args.kernel == "tuned" and not args.no_bf16:
-        # the BF16-operand kernels on the same workload, same steps and timing
-        b = measure(args, mesh, mats, "bf16", stream)
-        bi = b["info"]
-        out["bf16"] = {
-            "value": bi["updates_per_macro_step"] * args.steps / (b["ms"] / 1e3),
-            "ms_per_step": b["ms"] / args.steps,
-            "dtype": DTYPE["bf16"],
-            "launch": launch_record("bf16", bi),
-            "roofline": roofline(args, "bf16", bi, b["prof"]),
-            "kernels_ms": {k: v[0] for k, v in b["prof"].items()},
-        }
+        # the BF16-operand kernels (and, up to order 6, split BF16 operands)
+        # on the same workload, same steps and timing
+        for prec in ("bf16", "bf16x3") if args.order <= 6 else ("bf16",):
+            b = measure(args, mesh, mats, prec, stream)
+            bi = b["info"]
+            out[prec] = {
+                "value": bi["updates_per_macro_step"] * args.steps / (b["ms"] / 1e3),
+                "ms_per_step": b["ms"] / args.steps,
+                "dtype": DTYPE[prec],
+                "launch": launch_record(prec, bi),
+                "roofline": roofline(args, prec, bi, b["prof"]),
+                "kernels_ms": {k: v[0] for k, v in b["prof"].items()},
+            }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.order)
     print(json.dumps(out), flush=True)
@@ -445,7 +448,8 @@ def acoustic_fraction(inf):
 def launch_record(precision, inf):
     return {"predict": inf["launch"][:3], "correct": inf["launch"][3:7], "mc_min": inf["launch"][7],
             "predict_shape": {("fp32", 0): "I~ park LDS", ("fp32", 1): "I~ park HBM",
-                              ("bf16", 0): "bf16 16x16x16", ("bf16", 1): "bf16 16x16x32"}.get(
+                              ("bf16", 0): "bf16 16x16x16", ("bf16", 1): "bf16 16x16x32",
+                              ("bf16x3", 0): "split bf16 16x16x16"}.get(
                                   (precision, inf["shape"]), "plain"),
             "source": ["default", "measured", "cache"][inf["launch_source"]]}
 
