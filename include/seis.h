@@ -99,7 +99,8 @@ typedef struct {
 
 typedef struct {
   int precision;    /* SEIS_FP64 / SEIS_FP32 / SEIS_BF16 / SEIS_BF16_SPLIT (operands; FP32 accumulation) */
-  int kernel;       /* SEIS_KERNEL_TUNED (default) or SEIS_KERNEL_PLAIN */
+  int kernel;       /* SEIS_KERNEL_TUNED (default) or SEIS_KERNEL_PLAIN; FP64 has no
+                       matrix-core form and always runs the plain kernels */
   double cfl;       /* C in dt_K = C/(2N+1) h_K / c_p,K (Sec. 4.4); default 0.35 */
   double g;         /* gravitational acceleration (Sec. 3); default 9.81 */
   int max_clusters; /* rate-2 LTS clusters (Sec. 4.4); 1 = global time stepping */
@@ -173,11 +174,14 @@ void seis_default_options(seis_options_t *opt);
  * assemble geometry, element Jacobians and the per-face Godunov flux
  * matrices F-, F+ (Sec. 4.2, bilinear rewrite of the numerical flux) in FP64,
  * assign LTS clusters, allocate device state (all zero: Q = 0, eta = 0).
- * order: O = N + 1 in [3, 7]. opt may be NULL (defaults). On success *out
- * owns the handle; free it with seis_destroy.
+ * order: O = N + 1 in [2, 8] with the plain kernels, [3, 7] with the
+ * matrix-core kernels ([3, 6] with split BF16 operands); fault faces need
+ * O <= 7. opt may be NULL (defaults). On success *out owns the handle; free
+ * it with seis_destroy.
  * Errors: SEIS_EINVAL (degenerate element, unmatched interior or periodic
  * face, gravity face not acoustic or not horizontal with outward normal +z,
- * more than one gravity face per element, bad order), SEIS_ENOMEM, SEIS_EDEVICE. */
+ * more than one gravity face per element, order outside the kernels' range),
+ * SEIS_ENOMEM, SEIS_EDEVICE. */
 int seis_setup(const seis_mesh_t *mesh, const seis_materials_t *mat, int order,
                const seis_options_t *opt, seis_t **out);
 

@@ -535,7 +535,9 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
     return setup_fail(SEIS_EINVAL, "split BF16 supports orders 3..6 (its two LDS images of order 7 exceed a CU)");
   if (o.kernel == SEIS_KERNEL_PLAIN && (o.precision == SEIS_BF16 || o.precision == SEIS_BF16_SPLIT))
     return setup_fail(SEIS_EINVAL, "BF16 operands need the tuned (MFMA) kernels");
-  if (order < 3 || order > 7) return setup_fail(SEIS_EINVAL, "order must be in 3..7");
+  if (order < 2 || order > 8) return setup_fail(SEIS_EINVAL, "order must be in 2..8");
+  if (o.kernel == SEIS_KERNEL_TUNED && o.precision != SEIS_FP64 && (order < 3 || order > 7))
+    return setup_fail(SEIS_EINVAL, "the matrix-core kernels support orders 3..7 (orders 2 and 8: kernel plain)");
   if (o.mc_min < 0) return setup_fail(SEIS_EINVAL, "mc_min must be >= 0");
   int dev = 0;
   hipDeviceProp_t prop;
@@ -564,6 +566,11 @@ int seis_setup(const seis_mesh_t* mesh, const seis_materials_t* mat, int order, 
   if (!e.empty()) {
     delete h;
     return setup_fail(SEIS_EINVAL, e);
+  }
+  if (!h->M.f_elem.empty() && order > 7) {
+    // both sides' stored derivatives of an order-8 face exceed a work-group's LDS
+    delete h;
+    return setup_fail(SEIS_EINVAL, "fault faces support orders 2..7");
   }
   h->precision = o.precision;
   h->kernel = o.kernel;

@@ -210,7 +210,7 @@ hipError_t launch_fault(int N, const FaultArgs& a, const T* gD, T* In, int64_t f
   switch (N) {
 #define SEIS_F(NN) \
   case NN: hipLaunchKernelGGL((k_fault<T, NN>), dim3((unsigned)nf), dim3(kFaultThreads), 0, s, a, gD, In, f0); break;
-    SEIS_F(2) SEIS_F(3) SEIS_F(4) SEIS_F(5) SEIS_F(6)
+    SEIS_F(1) SEIS_F(2) SEIS_F(3) SEIS_F(4) SEIS_F(5) SEIS_F(6)
 #undef SEIS_F
     default: return hipErrorInvalidValue;
   }

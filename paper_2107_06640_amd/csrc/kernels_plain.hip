@@ -291,11 +291,13 @@ hipError_t grav_n(const DevData<T>& d, const int32_t* glist, int64_t ng, hipStre
 
 #define SEIS_DISPATCH(FN, ...)                  \
   switch (N) {                                  \
+    case 1: return FN<T, 1>(__VA_ARGS__);       \
     case 2: return FN<T, 2>(__VA_ARGS__);       \
     case 3: return FN<T, 3>(__VA_ARGS__);       \
     case 4: return FN<T, 4>(__VA_ARGS__);       \
     case 5: return FN<T, 5>(__VA_ARGS__);       \
     case 6: return FN<T, 6>(__VA_ARGS__);       \
+    case 7: return FN<T, 7>(__VA_ARGS__);       \
     default: return hipErrorInvalidValue;       \
   }
 

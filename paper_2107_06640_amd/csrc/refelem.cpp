@@ -210,7 +210,7 @@ int vertex_map_index(const RefElement& r, const int sigma[3]) {
 }
 
 RefElement build_reference(int N) {
-  if (N < 1 || N > 6) throw std::runtime_error("degree out of range");
+  if (N < 1 || N > 7) throw std::runtime_error("degree out of range");
   RefElement R;
   R.N = N;
   R.B = n_basis(N);

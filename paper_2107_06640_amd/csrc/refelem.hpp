@@ -47,7 +47,7 @@ struct RefElement {
 int n_basis(int N);
 int n_face_nodes(int N);
 
-// Build all reference matrices for degree N (1 <= N <= 6).
+// Build all reference matrices for degree N (1 <= N <= 7).
 RefElement build_reference(int N);
 
 // Gauss-Jacobi nodes and weights on [-1, 1] for weight (1-x)^alpha (1+x)^beta.

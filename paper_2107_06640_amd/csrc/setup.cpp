@@ -37,7 +37,7 @@ std::string build_model(int64_t nv, const double* xyz, int64_t E, const int64_t*
                         double cfl, double g, int max_clusters, Model& M) {
   std::ostringstream err;
   if (nv <= 0 || E <= 0 || !xyz || !tet || !face_kind || !rho || !lam || !mu) return "null or empty mesh/material array";
-  if (N < 2 || N > 6) return "order out of range (3..7)";
+  if (N < 1 || N > 7) return "order out of range (2..8)";
   if (!(cfl > 0.0) || !(g >= 0.0)) return "cfl must be > 0 and g >= 0";
   if (max_clusters < 1 || max_clusters > 16) return "max_clusters must be in 1..16";
   if (E > (int64_t(1) << 29)) return "too many elements";
