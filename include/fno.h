@@ -34,8 +34,9 @@ extern "C" {
  * transposes are stride choices), likewise B and C. Operands are rounded to
  * BF16 (nearest even) on load; products accumulate in FP32. split_k > 1
  * divides K among work-groups whose partial sums are added atomically (the
- * result is then not bitwise reproducible; beta is applied first). C must not
- * alias A or B. */
+ * result is then not bitwise reproducible; C is scaled by beta first);
+ * otherwise beta is applied in the product's own write. With beta = 0, C is
+ * not read. C must not alias A or B. */
 int fno_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, float alpha, const float *A, int64_t sAb,
              int64_t sAm, int64_t sAk, const float *B, int64_t sBb, int64_t sBk, int64_t sBn, float beta,
              float *C, int64_t sCb, int64_t sCm, int64_t sCn, int split_k, void *stream);

@@ -42,7 +42,8 @@ struct GemmArgs {
   int64_t tiles_n;  // ceil(N / 64)
   int64_t tiles_m;  // ceil(M / 64)
   int64_t kchunk;   // K range of one split (multiple of 32)
-  int atomic;       // add into C atomically (split K)
+  int atomic;       // add into C atomically (split K; C pre-scaled by beta)
+  float beta;       // C = alpha A B + beta C (without split K); 0: C is not read
 };
 
 constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 4;  // LDS rows padded (8-byte aligned fragments)
@@ -53,10 +54,13 @@ constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 4;  // LDS rows padded (8-by
 // column l%16; C lane l: rows 4(l/16)+v, column l%16). A and B place each k
 // value in the same (lane group, register slot), so the products pair the
 // right entries whatever order the instruction gives the slots. Tiles of A
-// and B are staged in LDS as BF16, both with k contiguous.
+// and B are staged in LDS as BF16, both with k contiguous. C tiles with a
+// unit stride are written through LDS, so that consecutive threads store
+// consecutive addresses, with beta applied in the same pass.
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ unsigned short sA[BM][LDK];
   __shared__ unsigned short sB[BN][LDK];
+  __shared__ float sC[BM][BN + 1];  // the output tile, for row- or column-contiguous writes
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   // work-group -> (batch, row tile, column tile), column tiles fastest
   const int64_t bx = blockIdx.x;
@@ -111,20 +115,42 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __syncthreads();
   }
   float* C = g.C + b * g.sCb;
+  if (g.atomic || (g.sCn != 1 && g.sCm != 1)) {
+    // split K (atomic adds into the pre-scaled C) or a C with no unit stride
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+          const int64_t n = n0 + wn * 32 + j * 16 + (lane & 15);
+          if (m >= g.M || n >= g.N) continue;
+          float* c = C + m * g.sCm + n * g.sCn;
+          const float x = g.alpha * acc[i][j][v];
+          if (g.atomic) atomicAdd(c, x);
+          else *c = g.beta == 0.0f ? x : x + g.beta * *c;
+        }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-        const int64_t n = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (m >= g.M || n >= g.N) continue;
-        float* c = C + m * g.sCm + n * g.sCn;
-        const float x = g.alpha * acc[i][j][v];
-        if (g.atomic) atomicAdd(c, x);
-        else *c += x;  // C was pre-scaled by beta
-      }
+      for (int v = 0; v < 4; ++v) sC[wm * 32 + i * 16 + 4 * (lane >> 4) + v][wn * 32 + j * 16 + (lane & 15)] = acc[i][j][v];
+  __syncthreads();
+  const bool rows = g.sCn == 1;  // else sCm == 1: walk m fastest
+#pragma unroll 4
+  for (int it = 0; it < BM * BN / 256; ++it) {
+    const int f = tid + 256 * it;
+    const int r = rows ? f >> 6 : f & 63, c = rows ? f & 63 : f >> 6;
+    const int64_t m = m0 + r, n = n0 + c;
+    if (m >= g.M || n >= g.N) continue;
+    float* p = C + m * g.sCm + n * g.sCn;
+    const float x = g.alpha * sC[r][c];
+    *p = g.beta == 0.0f ? x : x + g.beta * *p;
+  }
 }
 
 // C *= beta over the strided batch (beta = 0 writes zeros).
@@ -159,6 +185,34 @@ __global__ void k_gelu_bwd(int64_t n, const float* z, const float* da, float* dz
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dz[i] = da[i] * gelu_d(z[i]);
 }
+
+// The same two kernels four values at a time (16-byte accesses), for arrays
+// whose rows of S values start on 16-byte boundaries: the bias of a row is
+// read once instead of dividing every index by S.
+__global__ void k_bias_act4(int64_t rows, int64_t C, int64_t S4, f4* z, const float* bias, f4* a, int act) {
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+    const float bb = bias ? bias[r % C] : 0.0f;
+    f4* zr = z + r * S4;
+    f4* ar = a + r * S4;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < S4; j += (int64_t)gridDim.x * blockDim.x) {
+      f4 x = zr[j];
+      if (bias) {
+        x += bb;
+        if (ar != zr) zr[j] = x;
+      }
+      if (act) x = f4{gelu(x[0]), gelu(x[1]), gelu(x[2]), gelu(x[3])};
+      ar[j] = x;
+    }
+  }
+}
+__global__ void k_gelu_bwd4(int64_t n4, const f4* z, const f4* da, f4* dz) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+    const f4 x = z[i], d = da[i];
+    dz[i] = f4{d[0] * gelu_d(x[0]), d[1] * gelu_d(x[1]), d[2] * gelu_d(x[2]), d[3] * gelu_d(x[3])};
+  }
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 // work-groups (channel c, part q of gridDim.y): each sums a strided share of
 // the channel's n_outer x S values and adds it to db[c] (zeroed before)
@@ -264,17 +318,19 @@ int fno_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, float alpha, const 
   hipStream_t s = (hipStream_t)stream;
   const int64_t tiles_n = (N + BN - 1) / BN, tiles_m = (M + BM - 1) / BM;
   if (batch * tiles_n * tiles_m > (int64_t(1) << 31) - 1) return -1;
-  if (beta != 1.0f || K == 0) {
+  int64_t kchunk = K > 0 ? (K + split_k - 1) / split_k : BK;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  const int64_t splits = K > 0 ? (K + kchunk - 1) / kchunk : 1;
+  if (splits > 65535) return -1;
+  // beta goes into the product's own write, except with split K (the splits
+  // add atomically into C scaled beforehand) or without a product (K = 0)
+  if (K == 0 || (splits > 1 && beta != 1.0f)) {
     hipLaunchKernelGGL(k_scale_c, dim3(grid_for(batch * M * N)), dim3(256), 0, s, batch, M, N, C, sCb, sCm, sCn, beta);
     if (hipGetLastError() != hipSuccess) return -3;
   }
   if (K == 0) return 0;
-  int64_t kchunk = (K + split_k - 1) / split_k;
-  kchunk = (kchunk + BK - 1) / BK * BK;
-  const int64_t splits = (K + kchunk - 1) / kchunk;
-  if (splits > 65535) return -1;
   GemmArgs g{M, N, K, alpha, A, sAb, sAm, sAk, B, sBb, sBk, sBn, C, sCb, sCm, sCn, tiles_n, tiles_m, kchunk,
-             splits > 1 ? 1 : 0};
+             splits > 1 ? 1 : 0, beta};
   hipLaunchKernelGGL(k_gemm, dim3((unsigned)(batch * tiles_n * tiles_m), 1, (unsigned)splits), dim3(256), 0, s, g);
   return status(hipGetLastError());
 }
@@ -282,6 +338,14 @@ int fno_gemm(int64_t batch, int64_t M, int64_t N, int64_t K, float alpha, const 
 int fno_bias_act(int64_t n_outer, int64_t C, int64_t S, float* z, const float* bias, float* a, int act,
                  void* stream) {
   if (n_outer < 0 || C <= 0 || S <= 0 || !z || !a) return -1;
+  if (S % 4 == 0 && aligned16(z) && aligned16(a)) {
+    const int64_t rows = n_outer * C;
+    if (rows == 0) return 0;
+    const dim3 grid(std::min<unsigned>(grid_for(S / 4), 2048u), (unsigned)std::min<int64_t>(rows, 65535));
+    hipLaunchKernelGGL(k_bias_act4, grid, dim3(256), 0, (hipStream_t)stream, rows, C, S / 4, reinterpret_cast<f4*>(z),
+                       bias, reinterpret_cast<f4*>(a), act);
+    return status(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_bias_act, dim3(grid_for(n_outer * C * S)), dim3(256), 0, (hipStream_t)stream, n_outer, C, S,
                      z, bias, a, act);
   return status(hipGetLastError());
@@ -289,6 +353,12 @@ int fno_bias_act(int64_t n_outer, int64_t C, int64_t S, float* z, const float* b
 
 int fno_gelu_backward(int64_t n, const float* z, const float* da, float* dz, void* stream) {
   if (n < 0 || !z || !da || !dz) return -1;
+  if (n % 4 == 0 && aligned16(z) && aligned16(da) && aligned16(dz)) {
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_gelu_bwd4, dim3(grid_for(n / 4)), dim3(256), 0, (hipStream_t)stream, n / 4,
+                       reinterpret_cast<const f4*>(z), reinterpret_cast<const f4*>(da), reinterpret_cast<f4*>(dz));
+    return status(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_gelu_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, n, z, da, dz);
   return status(hipGetLastError());
 }
