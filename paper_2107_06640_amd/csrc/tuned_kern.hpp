@@ -695,14 +695,12 @@ __device__ __forceinline__ void ck_step(const float (&din)[RTI][4][9], float (&d
 
 // First CK step straight from Q in memory (group base Qg): the stress rows of
 // D1 read only the velocity columns of D0 and the velocity rows only the
-// stress columns, so D0 is brought in one half at a time.
-template <class Op, int N, bool AC, int P0, int P1, int C0, int C1>
-__device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1))][4][9], const float* Qg,
-                                              int lane, const RefT<Op>* lds, const float* G, float lam, float mu,
-                                              float rinv, int el, int g, float* gd) {
-  constexpr int B = nbasis(N), RT = row_tiles(B), RT1 = row_tiles(nbasis(N - 1));
+// stress columns, so D0 is brought in as two column sets, both requested
+// before the first products.
+template <int N, bool AC, int C0, int C1>
+__device__ __forceinline__ void load_q_cols(float (&din)[row_tiles(nbasis(N))][4][9], const float* Qg, int lane) {
+  constexpr int B = nbasis(N), RT = row_tiles(B);
   const GroupBuf qb(Qg, RT * 36 * 256, lane);
-  float din[RT][4][9];
 #pragma unroll
   for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -714,6 +712,14 @@ __device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1
       for (int p = 0; p < 9; ++p)
         din[t][v][p] = (p >= C0 && p < C1 && carried<AC>(p) && 16 * t + 4 * v < B) ? qb.ld((t * 4 + v) * 9 + p) : 0.0f;
     }
+}
+
+template <class Op, int N, bool AC, int P0, int P1, int C0, int C1>
+__device__ __forceinline__ void ck_first_half(float (&d1)[row_tiles(nbasis(N - 1))][4][9],
+                                              const float (&din)[row_tiles(nbasis(N))][4][9], const RefT<Op>* lds,
+                                              const float* G, float lam, float mu, float rinv, int el, int g,
+                                              float* gd) {
+  constexpr int B = nbasis(N), RT = row_tiles(B), RT1 = row_tiles(nbasis(N - 1));
   if (gd) {
 #pragma unroll
     for (int t = 0; t < RT; ++t)
@@ -734,11 +740,16 @@ struct CK {
   __device__ static __forceinline__ void run(float (&J)[row_tiles(nbasis(N - 1))][4][9], const float* Qg, int lane,
                              const RefT<Op>* lds, const float* G, float lam, float mu, float rinv, int el, int g,
                              float* gd) {
-    constexpr int B = nbasis(N);
+    constexpr int B = nbasis(N), RT = row_tiles(B);
     constexpr int R1 = row_tiles(nbasis(N - 1));
-    ck_first_half<Op, N, AC, 0, 6, 6, 9>(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
-    __builtin_amdgcn_sched_barrier(0);
-    ck_first_half<Op, N, AC, 6, 9, 0, 6>(J, Qg, lane, lds, G, lam, mu, rinv, el, g, gd);
+    {
+      float dv[RT][4][9], ds[RT][4][9];
+      load_q_cols<N, AC, 6, 9>(dv, Qg, lane);
+      load_q_cols<N, AC, 0, 6>(ds, Qg, lane);
+      ck_first_half<Op, N, AC, 0, 6, 6, 9>(J, dv, lds, G, lam, mu, rinv, el, g, gd);
+      __builtin_amdgcn_sched_barrier(0);
+      ck_first_half<Op, N, AC, 6, 9, 0, 6>(J, ds, lds, G, lam, mu, rinv, el, g, gd);
+    }
     if (gd) store_deriv<N, AC>(gd + 1 * B * 9, J, g);
 #pragma unroll
     for (int t = 0; t < R1; ++t)
