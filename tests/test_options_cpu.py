@@ -19,7 +19,10 @@ LIB = os.path.join(ROOT, "paper_2107_06640_amd", "libseis.so")
     (dict(mc_min=-1), 4, "mc_min"),
     (dict(precision="bf16", kernel="plain"), 4, "BF16"),
     (dict(), 9, "order"),
-    (dict(), 2, "order"),
+    (dict(), 1, "order"),
+    (dict(precision="fp32"), 2, "3..7"),
+    (dict(precision="bf16"), 8, "3..7"),
+    (dict(precision="bf16x3"), 7, "3..6"),
 ])
 def test_setup_rejects_bad_options(kw, order, word):
     from paper_2107_06640_amd import seis
