@@ -11,7 +11,7 @@
  * Fourier transform, a per-mode complex channel mixing and the inverse
  * transform, then a pointwise projection. Every transform and mixing step is
  * a (batched) matrix product, so the library exports one general strided
- * batched product plus the elementwise kernels; the model driver composes
+ * batched product plus the elementwise kernels; the network code composes
  * them (paper_2107_06640_amd/fno.py).
  *
  * All pointers are device pointers (FP32 unless stated), owned by the

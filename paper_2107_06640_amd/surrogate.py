@@ -29,7 +29,8 @@ raises through the elastic solid, the ocean and the gravity surface
    number of training runs).
 4. Use (Surrogate): inputs outside the training ranges, or outputs that are
    not finite or exceed the physically possible amplitude, are answered by
-   the solver instead (the solver is the fallback and the judge).
+   the solver instead (the solver is the fallback and the reference that
+   checks the network).
 """
 from __future__ import annotations
 
@@ -230,7 +231,7 @@ def rel_l2(a, b):
 
 
 class Surrogate:
-    """The trained network with the solver as fallback and judge."""
+    """The trained network with the solver as fallback and reference."""
 
     def __init__(self, net, y_scale, solver, lx, ly):
         self.net, self.y_scale, self.solver, self.lx, self.ly = net, y_scale, solver, lx, ly

@@ -2,9 +2,9 @@
 
 Implements the calls of paper_2107_06640_amd.fno.Kernels with torch CPU
 tensors in the tensors' own precision (float64 in the tests), reading and
-writing through the same strides and offsets the driver passes, and checking
+writing through the same strides and offsets the network code (fno.py) passes, and checking
 that every strided view stays inside its tensor. It lets the CPU tests check
-the driver's composition of products (its layouts and strides) against the
+the network's composition of products (its layouts and strides) against the
 FFT-based oracle before any kernel runs on a GPU.
 """
 import torch

@@ -1,4 +1,4 @@
-"""CPU checks of the surrogate: oracle pins, and the driver's composition of
+"""CPU checks of the surrogate: oracle pins, and the network's composition of
 products (through CPU stand-in kernels) against the oracle.
 
 Pins of the oracle (independent of its own code path):
@@ -73,7 +73,7 @@ def test_adam_first_step_is_signed_learning_rate():
 
 
 @pytest.mark.parametrize("shape", [(8, 8, 8, 2, 3), (12, 8, 6, 3, 2)])
-def test_driver_composition_matches_oracle(shape):
+def test_network_composition_matches_oracle(shape):
     from paper_2107_06640_amd.fno import FNO
     X, Y, T, m, B = shape
     cin, W, L, H = 3, 4, 2, 5

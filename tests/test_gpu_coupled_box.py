@@ -124,7 +124,7 @@ def test_200_steps_reduced_precision_against_fp64():
     weights, each field against its own norm) and on eta. Bars: FP32 1e-4
     (its round-off accumulates to about 1e-5 here), split BF16 3e-3 (17-bit
     operands), BF16 reported with the sanity bar 1 (8-bit operands; its
-    accuracy is judged against the discretisation error elsewhere)."""
+    accuracy is compared with the discretisation error in the accuracy tests)."""
     from paper_2107_06640_amd import seis
     mesh, mats = inputs.cfg2()
     X = mesh.xyz[mesh.tet]
