@@ -278,11 +278,9 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--mc-min", type=int, default=None,
                     help="clusters with fewer elements run on the plain FP32 kernels (library default 2048)")
-    ap.add_argument("--graph", dest="graph", action="store_true", default=True,
-                    help="(default) replay each macro step as one hipGraph; kernel timings then come "
-                         "from a separate eagerly launched pass of the same length")
-    ap.add_argument("--eager", dest="graph", action="store_false",
-                    help="launch every kernel of the timed steps from the host instead of a hipGraph")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay each macro step as one hipGraph; kernel timings then come from a "
+                         "separate eagerly launched pass of the same length")
     ap.add_argument("--nine-quantity-water", action="store_true",
                     help="acoustic elements in the nine-quantity embedding everywhere (no 4-quantity groups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -389,7 +387,7 @@ def measure(args, mesh, mats, precision, stream):
     """Set up the solver, warm up, and time args.steps macro steps on the library's stream.
 
     Returns the solver info, the event-timed milliseconds of the timed steps
-    (graph replays unless --eager), those of an eagerly launched pass, and the
+    (graph replays with --graph), those of an eagerly launched pass, and the
     per-kernel profile (milliseconds, launches, elements) of the eager pass.
     """
     import torch
